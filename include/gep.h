@@ -1,0 +1,145 @@
+/*
+ * libgep: dense generalized symmetric-definite eigensolver for one AMD MI355X
+ * (gfx950) GPU.
+ *
+ * Problem (section 1, Eq. 1; section 3.1, Eq. 2): given real symmetric M x M
+ * matrices A and B with B positive definite, find all eigenvalues lambda_k and
+ * eigenvectors y_k with  A y_k = lambda_k B y_k,  i.e.  A Y = B Y Lambda  with the
+ * normalisation  Y^T B Y = I.
+ *
+ * Method (section 3.1, Eqs. 3-6, written with L = U^T):
+ *   reducer     B = L L^T (Eq. 4), C = L^{-1} A L^{-T} (Eq. 5) formed without an
+ *               explicit inverse of L;
+ *   SEP solver  C -> band -> tridiagonal (two-stage Householder reduction),
+ *               tridiagonal divide and conquer, back transformation through both
+ *               Householder stages (the TRD/BAND, D&C and BACK phases of Table 3);
+ *   back        Y = L^{-T} Z (Eq. 6).
+ *
+ * Conventions for every entry point:
+ *   - matrices are column-major with a leading dimension, FP64;
+ *   - every matrix and vector pointer is a DEVICE pointer, except arrays whose
+ *     name ends in _host;
+ *   - only the LOWER triangle of a symmetric input is read; inputs are never
+ *     modified;
+ *   - work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ *     asynchronous: outputs are valid once the stream has reached that point;
+ *   - the caller owns every buffer, including the workspace (size from the
+ *     matching *_workspace_size function); the library keeps no pointer after
+ *     return and does not allocate device memory on these paths;
+ *   - argument errors are detected on the host before any device work and return
+ *     a negative gep_status synchronously (gep_last_bad_arg() names the 1-based
+ *     argument); HIP errors return GEP_ERR_HIP;
+ *   - numerical failures are reported asynchronously in the device int32 `info`
+ *     (LAPACK generalized-driver convention): 0 = success; k in [1, M] = the
+ *     tridiagonal eigensolver did not converge for eigenvalue k; M + k = the
+ *     leading minor of order k of B is not positive definite.
+ *   - M = 0 is a no-op.
+ *
+ * Eigenvalues are returned in ascending order; for each eigenvector the entry of
+ * largest magnitude is positive (lowest index on ties).
+ */
+#ifndef GEP_H
+#define GEP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GEP_OK = 0,
+  GEP_ERR_ARG = -1,        /* invalid argument: see gep_last_bad_arg() */
+  GEP_ERR_WORKSPACE = -2,  /* workspace smaller than the *_workspace_size value */
+  GEP_ERR_HIP = -3,        /* a HIP runtime call failed */
+  GEP_ERR_NO_DEVICE = -4,  /* no usable gfx950 device */
+  GEP_ERR_INTERNAL = -5
+} gep_status;
+
+typedef enum { GEP_JOB_VALUES = 0, GEP_JOB_VECTORS = 1 } gep_job;
+typedef enum { GEP_PREC_FP64 = 0, GEP_PREC_MIXED = 1 } gep_prec;
+
+/* Human-readable name of a gep_status value. */
+const char* gep_status_string(int status);
+/* 1-based index of the offending argument of the last GEP_ERR_ARG (per thread). */
+int gep_last_bad_arg(void);
+/* Library version string. */
+const char* gep_version(void);
+
+/* Bytes of workspace gep_solve needs for order M. */
+size_t gep_workspace_size(int64_t M, int job, int prec);
+
+/*
+ * Solve A Y = B Y Lambda (all eigenpairs, or eigenvalues only for
+ * job = GEP_JOB_VALUES, the paper's T_evo case of section 4).
+ *   A [lda x M], B [ldb x M]: lower triangles read.
+ *   lambda [M]: eigenvalues, ascending.
+ *   Y [ldy x M]: B-orthonormal eigenvectors (unused and may be NULL for VALUES).
+ *   prec: GEP_PREC_FP64 (every step in FP64).
+ *   workspace: >= gep_workspace_size(M, job, prec) bytes, 256-byte aligned.
+ *   info: device int32, see above.
+ */
+int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+              double* lambda, double* Y, int64_t ldy, int job, int prec, void* workspace,
+              size_t ws_bytes, int32_t* info, void* stream);
+
+/*
+ * Phase entry points (same conventions).  They expose the steps of gep_solve one
+ * at a time so that each can be checked and timed on its own.
+ *
+ * gep_reduce: reducer of section 3.1 (Eqs. 4-5).  L [ldl x M] receives the
+ *   Cholesky factor (strict upper triangle zero), C [ldc x M] the reduced matrix
+ *   L^{-1} A L^{-T} (full symmetric).  info as for gep_solve (M + k only).
+ */
+size_t gep_reduce_workspace_size(int64_t M);
+int gep_reduce(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb, double* L,
+               int64_t ldl, double* C, int64_t ldc, void* workspace, size_t ws_bytes,
+               int32_t* info, void* stream);
+
+/*
+ * gep_band_reduce: first stage of the two-stage reduction (TRD/BAND of Table 3):
+ *   symmetric C (lower read) -> band matrix with the same eigenvalues, returned in
+ *   lower band storage: element (i, j), 0 <= i - j <= band_width, at
+ *   band[(i - j) + j * ldband], ldband >= band_width + 1.
+ *   band_width: 1..64, or 0 for the value gep_solve uses.
+ */
+size_t gep_band_reduce_workspace_size(int64_t M, int band_width);
+int gep_band_reduce(int64_t M, const double* C, int64_t ldc, int band_width, double* band,
+                    int64_t ldband, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * gep_tridiagonalize: both stages: symmetric C (lower read) -> symmetric
+ *   tridiagonal T with the same eigenvalues: d [M] diagonal, e [M-1] subdiagonal.
+ */
+size_t gep_tridiagonalize_workspace_size(int64_t M, int band_width);
+int gep_tridiagonalize(int64_t M, const double* C, int64_t ldc, int band_width, double* d,
+                       double* e, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * gep_tridiag_eig: eigen-decomposition of the symmetric tridiagonal (d, e) (D&C
+ *   phase of Table 3): lambda [M] ascending; for job = GEP_JOB_VECTORS, Z [ldz x M]
+ *   orthonormal eigenvectors (divide and conquer); for GEP_JOB_VALUES, Sturm
+ *   bisection and Z unused.  info: k in [1, M] on non-convergence.
+ */
+size_t gep_tridiag_eig_workspace_size(int64_t M, int job);
+int gep_tridiag_eig(int64_t M, const double* d, const double* e, double* lambda, double* Z,
+                    int64_t ldz, int job, void* workspace, size_t ws_bytes, int32_t* info,
+                    void* stream);
+
+/*
+ * Per-phase timing of the last gep_solve on this process: when enabled,
+ * gep_solve records HIP events around its phases on `stream`.
+ * gep_profile_read synchronises on the last event and writes up to n phase times
+ * in milliseconds, in the order R1 (Cholesky), R2-4 (reduced matrix), S1 (full ->
+ * band), S2 (band -> tridiagonal), S3 (tridiagonal eigensolver), S4 (Q2), S5 (Q1),
+ * R5 (Y = L^{-T} Z), F (sort / sign).  Returns the number of phases written.
+ */
+int gep_profile_enable(int on);
+int gep_profile_read(double* ms, int n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GEP_H */

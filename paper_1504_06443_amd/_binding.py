@@ -1,0 +1,94 @@
+"""ctypes declarations of the libgep C ABI (include/gep.h)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libgep.so"
+
+JOB_VALUES = 0
+JOB_VECTORS = 1
+PREC_FP64 = 0
+PREC_MIXED = 1
+
+GEP_OK = 0
+GEP_ERR_ARG = -1
+GEP_ERR_WORKSPACE = -2
+GEP_ERR_HIP = -3
+
+
+class GEPError(RuntimeError):
+    def __init__(self, status: int, where: str, bad_arg: int = 0):
+        msg = f"{where}: {status_string(status)} (status {status})"
+        if status == GEP_ERR_ARG:
+            msg += f", argument {bad_arg}"
+        super().__init__(msg)
+        self.status = status
+        self.bad_arg = bad_arg
+
+
+def lib_path() -> str:
+    return os.path.join(HERE, _LIB_NAME)
+
+
+_lib = None
+
+P = ctypes.c_void_p
+I64 = ctypes.c_int64
+INT = ctypes.c_int
+SZ = ctypes.c_size_t
+DBL = ctypes.c_double
+
+# name -> (restype, argtypes)
+SIGNATURES = {
+    "gep_status_string": (ctypes.c_char_p, [INT]),
+    "gep_last_bad_arg": (INT, []),
+    "gep_version": (ctypes.c_char_p, []),
+    "gep_workspace_size": (SZ, [I64, INT, INT]),
+    "gep_solve": (INT, [I64, P, I64, P, I64, P, P, I64, INT, INT, P, SZ, P, P]),
+    "gep_reduce_workspace_size": (SZ, [I64]),
+    "gep_reduce": (INT, [I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P, P]),
+    "gep_band_reduce_workspace_size": (SZ, [I64, INT]),
+    "gep_band_reduce": (INT, [I64, P, I64, INT, P, I64, P, SZ, P]),
+    "gep_tridiagonalize_workspace_size": (SZ, [I64, INT]),
+    "gep_tridiagonalize": (INT, [I64, P, I64, INT, P, P, P, SZ, P]),
+    "gep_tridiag_eig_workspace_size": (SZ, [I64, INT]),
+    "gep_tridiag_eig": (INT, [I64, P, P, P, P, I64, INT, P, SZ, P, P]),
+    "gep_profile_enable": (INT, [INT]),
+    "gep_profile_read": (INT, [P, INT]),
+}
+
+
+def lib():
+    """Load libgep.so (built in place by paper_1504_06443_amd/build.py)."""
+    global _lib
+    if _lib is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"{path} is missing: build it with "
+                               f"`python -m paper_1504_06443_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(path)
+        for name, (res, args) in SIGNATURES.items():
+            if hasattr(L, name):
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def status_string(status: int) -> str:
+    try:
+        return lib().gep_status_string(status).decode()
+    except Exception:
+        return "unknown"
+
+
+def check(status: int, where: str) -> None:
+    if status != GEP_OK:
+        raise GEPError(status, where, lib().gep_last_bad_arg())
+
+
+def workspace_size(M: int, job: int = JOB_VECTORS, prec: int = PREC_FP64) -> int:
+    return int(lib().gep_workspace_size(M, job, prec))

@@ -1,0 +1,502 @@
+// C ABI of libgep: argument validation on the host, workspace planning, and the
+// phase sequence of the solver (reducer, two-stage reduction, tridiagonal
+// eigensolver, back transformations).
+#include <cstring>
+#include <exception>
+
+#include "../../include/gep.h"
+#include "common.h"
+#include "internal.h"
+
+namespace gep {
+namespace {
+
+thread_local int g_bad_arg = 0;
+
+int bad(int idx) {
+  g_bad_arg = idx;
+  return GEP_ERR_ARG;
+}
+
+int default_band(int64_t M) {
+  if (M >= 2048) return 64;
+  if (M >= 256) return 32;
+  return 16;
+}
+
+// ---------------------------------------------------------------- finishing
+__global__ void sign_fix_kernel(int64_t n, double* __restrict__ Y, int64_t ldy) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  double* y = Y + (int64_t)blockIdx.x * ldy;
+  double best = -1.0;
+  int64_t idx = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const double a = fabs(y[i]);
+    if (a > best) { best = a; idx = i; }
+  }
+  bv[threadIdx.x] = best;
+  bi[threadIdx.x] = idx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      const double o = bv[threadIdx.x + s];
+      const int64_t oi = bi[threadIdx.x + s];
+      if (o > bv[threadIdx.x] || (o == bv[threadIdx.x] && oi < bi[threadIdx.x])) {
+        bv[threadIdx.x] = o;
+        bi[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (y[bi[0]] < 0.0)
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) y[i] = -y[i];
+}
+
+__global__ void band_copy_out(int64_t n, int b, const double* __restrict__ band, int64_t ldw,
+                              double* __restrict__ out, int64_t ldo) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  for (int d = 0; d <= b; ++d) out[d + j * ldo] = (j + d < n) ? band[d + j * ldw] : 0.0;
+}
+
+// ---------------------------------------------------------------- profiling
+constexpr int NPHASE = 9;
+bool g_prof = false;
+hipEvent_t g_ev[NPHASE + 1];
+bool g_ev_ok = false;
+bool g_ev_recorded = false;
+
+struct Prof {
+  hipStream_t s;
+  explicit Prof(hipStream_t st) : s(st) {
+    if (g_prof && !g_ev_ok) {
+      for (int i = 0; i <= NPHASE; ++i) GEP_HIP(hipEventCreate(&g_ev[i]));
+      g_ev_ok = true;
+    }
+  }
+  void mark(int i) {
+    if (g_prof) GEP_HIP(hipEventRecord(g_ev[i], s));
+    if (g_prof && i == NPHASE) g_ev_recorded = true;
+  }
+};
+
+// ---------------------------------------------------------------- workspace plan
+struct Plan {
+  int64_t M;
+  int b;
+  int64_t ldband, kmax, nblk;
+  bool vectors;
+  double *L, *Linv, *tmp, *C, *T1, *band, *d, *e, *V2, *tau2, *bounds;
+  int32_t *sync, *err;
+  char* scratch;  // phase scratch (reused by S1, S3, S4, S5)
+  size_t scratch_bytes;
+};
+
+size_t phase_scratch_bytes(int64_t M, int b, bool vectors) {
+  size_t s = sy2sb_workspace(M, b);
+  if (vectors) {
+    s = s > stedc_workspace(M) ? s : stedc_workspace(M);
+    const size_t q2 = apply_q2_workspace(M, b);
+    s = s > q2 ? s : q2;
+    const size_t q1 = (size_t)2 * b * M * sizeof(double) + 1024;
+    s = s > q1 ? s : q1;
+  }
+  return s;
+}
+
+void carve(Plan& p, Arena& a, int64_t M, bool vectors) {
+  p.M = M;
+  p.b = default_band(M);
+  p.vectors = vectors;
+  p.ldband = 2 * p.b + 1;
+  p.kmax = M > 1 ? cdiv(M - 1, p.b) : 1;
+  p.nblk = cdiv(M, NB);
+  p.L = a.take<double>((size_t)M * M);
+  p.Linv = a.take<double>((size_t)p.nblk * NB * NB);
+  p.tmp = a.take<double>((size_t)NB * M);
+  p.C = a.take<double>((size_t)M * M);
+  p.T1 = a.take<double>((size_t)cdiv(M, p.b) * p.b * p.b);
+  p.band = a.take<double>((size_t)p.ldband * M);
+  p.d = a.take<double>(M);
+  p.e = a.take<double>(M);
+  p.bounds = a.take<double>(2);
+  p.sync = a.take<int32_t>(M + 8);
+  p.err = a.take<int32_t>(1);
+  if (vectors) {
+    const size_t nref = sb2st_reflector_count(M, p.b);
+    p.V2 = a.take<double>(nref * p.b);
+    p.tau2 = a.take<double>(nref);
+  } else {
+    p.V2 = p.tau2 = nullptr;
+  }
+  p.scratch_bytes = phase_scratch_bytes(M, p.b, vectors);
+  p.scratch = a.take<char>(p.scratch_bytes);
+}
+
+Arena scratch_arena(const Plan& p) {
+  Arena a;
+  a.base = p.scratch;
+  a.cap = p.scratch_bytes;
+  return a;
+}
+
+void reduce_steps(const Plan& p, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  int32_t* info, hipStream_t s, Prof* prof) {
+  const int64_t M = p.M;
+  // R1: L = chol(B)
+  copy_matrix(M, M, B, ldb, p.L, M, s);
+  potrf_rec(p.L, M, M, 0, p.Linv, info, M, p.tmp, s);
+  if (prof) prof->mark(1);
+  // R2-4: C = L^{-1} A L^{-T}
+  symmetrize_from_lower(M, A, lda, p.C, M, s);
+  Tri t{p.L, M, p.Linv, 0};
+  trsm_lln(t, M, p.C, M, M, p.tmp, s);
+  trsm_rlt_lower(t, M, p.C, M, p.tmp, s);
+  if (prof) prof->mark(2);
+}
+
+BandReduction band_of(const Plan& p) {
+  BandReduction r;
+  r.n = p.M; r.b = p.b; r.C = p.C; r.ldc = p.M; r.T = p.T1; r.band = p.band; r.ldband = p.ldband;
+  return r;
+}
+
+BulgeChase chase_of(const Plan& p) {
+  BulgeChase c;
+  c.n = p.M; c.b = p.b; c.band = p.band; c.ldband = p.ldband; c.d = p.d; c.e = p.e;
+  c.V = p.V2; c.tau = p.tau2; c.kmax = p.kmax; c.sync = p.sync; c.err = p.err;
+  return c;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    if (e.err == hipErrorOutOfMemory) return GEP_ERR_WORKSPACE;
+    return GEP_ERR_HIP;
+  } catch (...) {
+    return GEP_ERR_INTERNAL;
+  }
+}
+
+}  // namespace
+}  // namespace gep
+
+using namespace gep;
+
+extern "C" {
+
+const char* gep_status_string(int status) {
+  switch (status) {
+    case GEP_OK: return "ok";
+    case GEP_ERR_ARG: return "invalid argument";
+    case GEP_ERR_WORKSPACE: return "workspace too small";
+    case GEP_ERR_HIP: return "HIP runtime error";
+    case GEP_ERR_NO_DEVICE: return "no gfx950 device";
+    case GEP_ERR_INTERNAL: return "internal error";
+    default: return "unknown status";
+  }
+}
+
+int gep_last_bad_arg(void) { return g_bad_arg; }
+
+const char* gep_version(void) { return "libgep 0.1 (gfx950, FP64)"; }
+
+size_t gep_workspace_size(int64_t M, int job, int prec) {
+  (void)prec;
+  if (M <= 0) return 256;
+  Plan p;
+  Arena a;
+  a.dry = true;
+  carve(p, a, M, job == GEP_JOB_VECTORS);
+  return a.used + 256;
+}
+
+int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+              double* lambda, double* Y, int64_t ldy, int job, int prec, void* workspace,
+              size_t ws_bytes, int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (M > 0 && !lambda) return bad(6);
+  if (job != GEP_JOB_VALUES && job != GEP_JOB_VECTORS) return bad(9);
+  if (job == GEP_JOB_VECTORS) {
+    if (M > 0 && !Y) return bad(7);
+    if (ldy < m1) return bad(8);
+  }
+  if (prec != GEP_PREC_FP64) return bad(10);
+  if (!info) return bad(13);
+  const size_t need = gep_workspace_size(M, job, prec);
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(11);
+  if (ws_bytes < need) return GEP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    fill_i32(info, 1, 0, s);
+    if (M == 0) return GEP_OK;
+    const bool vectors = job == GEP_JOB_VECTORS;
+    Plan p;
+    Arena a;
+    a.base = (char*)workspace;
+    a.cap = ws_bytes;
+    carve(p, a, M, vectors);
+    Prof prof(s);
+    prof.mark(0);
+    reduce_steps(p, A, lda, B, ldb, info, s, &prof);
+    {
+      Arena sa = scratch_arena(p);
+      sy2sb(band_of(p), sa, s);
+    }
+    prof.mark(3);
+    sb2st(chase_of(p), s);
+    prof.mark(4);
+    if (!vectors) {
+      stebz_ws(M, p.d, p.e, lambda, p.bounds, s);
+      for (int i = 5; i <= 9; ++i) prof.mark(i);
+      return GEP_OK;
+    }
+    {
+      Arena sa = scratch_arena(p);
+      stedc(M, p.d, p.e, lambda, Y, ldy, info, sa, s);
+    }
+    prof.mark(5);
+    {
+      Arena sa = scratch_arena(p);
+      apply_q2(chase_of(p), Y, ldy, M, sa, s);
+    }
+    prof.mark(6);
+    {
+      Arena sa = scratch_arena(p);
+      apply_q1(band_of(p), Y, ldy, M, sa, s);
+    }
+    prof.mark(7);
+    trsm_llt(Tri{p.L, M, p.Linv, 0}, M, Y, ldy, M, p.tmp, s);
+    prof.mark(8);
+    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
+    GEP_LAUNCH_CHECK();
+    prof.mark(9);
+    return GEP_OK;
+  });
+}
+
+size_t gep_reduce_workspace_size(int64_t M) {
+  if (M <= 0) return 256;
+  Arena a;
+  a.dry = true;
+  a.take<double>((size_t)cdiv(M, NB) * NB * NB);
+  a.take<double>((size_t)NB * M);
+  return a.used + 256;
+}
+
+int gep_reduce(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb, double* L,
+               int64_t ldl, double* C, int64_t ldc, void* workspace, size_t ws_bytes,
+               int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (M > 0 && !L) return bad(6);
+  if (ldl < m1) return bad(7);
+  if (M > 0 && !C) return bad(8);
+  if (ldc < m1) return bad(9);
+  if (!info) return bad(12);
+  if (ws_bytes < gep_reduce_workspace_size(M)) return GEP_ERR_WORKSPACE;
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(10);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    fill_i32(info, 1, 0, s);
+    if (M == 0) return GEP_OK;
+    Arena a;
+    a.base = (char*)workspace;
+    a.cap = ws_bytes;
+    double* linv = a.take<double>((size_t)cdiv(M, NB) * NB * NB);
+    double* tmp = a.take<double>((size_t)NB * M);
+    copy_matrix(M, M, B, ldb, L, ldl, s);
+    potrf_rec(L, ldl, M, 0, linv, info, M, tmp, s);
+    symmetrize_from_lower(M, A, lda, C, ldc, s);
+    Tri t{L, ldl, linv, 0};
+    trsm_lln(t, M, C, ldc, M, tmp, s);
+    trsm_rlt_lower(t, M, C, ldc, tmp, s);
+    // outputs: L with zero strict upper triangle, C full symmetric
+    zero_upper(M, L, ldl, s);
+    symmetrize_from_lower(M, C, ldc, C, ldc, s);
+    return GEP_OK;
+  });
+}
+
+size_t gep_band_reduce_workspace_size(int64_t M, int band_width) {
+  if (M <= 0) return 256;
+  const int b = band_width > 0 ? band_width : default_band(M);
+  Arena a;
+  a.dry = true;
+  a.take<double>((size_t)M * M);
+  a.take<double>((size_t)cdiv(M, b) * b * b);
+  a.take<double>((size_t)(2 * b + 1) * M);
+  a.take<char>(sy2sb_workspace(M, b));
+  return a.used + 256;
+}
+
+int gep_band_reduce(int64_t M, const double* C, int64_t ldc, int band_width, double* band,
+                    int64_t ldband, void* workspace, size_t ws_bytes, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !C) return bad(2);
+  if (ldc < m1) return bad(3);
+  if (band_width < 0 || band_width > 64) return bad(4);
+  const int b = band_width > 0 ? band_width : default_band(M);
+  if (M > 0 && !band) return bad(5);
+  if (ldband < b + 1) return bad(6);
+  if (ws_bytes < gep_band_reduce_workspace_size(M, band_width)) return GEP_ERR_WORKSPACE;
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(7);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    if (M == 0) return GEP_OK;
+    Arena a;
+    a.base = (char*)workspace;
+    a.cap = ws_bytes;
+    BandReduction r;
+    r.n = M; r.b = b;
+    r.C = a.take<double>((size_t)M * M);
+    r.ldc = M;
+    r.T = a.take<double>((size_t)cdiv(M, b) * b * b);
+    r.ldband = 2 * b + 1;
+    r.band = a.take<double>((size_t)r.ldband * M);
+    Arena sa;
+    sa.cap = sy2sb_workspace(M, b);
+    sa.base = a.take<char>(sa.cap);
+    copy_matrix(M, M, C, ldc, r.C, M, s);
+    sy2sb(r, sa, s);
+    hipLaunchKernelGGL(band_copy_out, dim3((unsigned)cdiv(M, 256)), dim3(256), 0, s, M, b,
+                       (const double*)r.band, r.ldband, band, ldband);
+    GEP_LAUNCH_CHECK();
+    return GEP_OK;
+  });
+}
+
+size_t gep_tridiagonalize_workspace_size(int64_t M, int band_width) {
+  if (M <= 0) return 256;
+  const int b = band_width > 0 ? band_width : default_band(M);
+  Arena a;
+  a.dry = true;
+  a.take<double>((size_t)M * M);
+  a.take<double>((size_t)cdiv(M, b) * b * b);
+  a.take<double>((size_t)(2 * b + 1) * M);
+  a.take<int32_t>(M + 8);
+  a.take<int32_t>(1);
+  a.take<char>(sy2sb_workspace(M, b));
+  return a.used + 256;
+}
+
+int gep_tridiagonalize(int64_t M, const double* C, int64_t ldc, int band_width, double* d,
+                       double* e, void* workspace, size_t ws_bytes, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !C) return bad(2);
+  if (ldc < m1) return bad(3);
+  if (band_width < 0 || band_width > 64) return bad(4);
+  const int b = band_width > 0 ? band_width : default_band(M);
+  if (M > 0 && !d) return bad(5);
+  if (M > 1 && !e) return bad(6);
+  if (ws_bytes < gep_tridiagonalize_workspace_size(M, band_width)) return GEP_ERR_WORKSPACE;
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(7);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    if (M == 0) return GEP_OK;
+    Arena a;
+    a.base = (char*)workspace;
+    a.cap = ws_bytes;
+    BandReduction r;
+    r.n = M; r.b = b;
+    r.C = a.take<double>((size_t)M * M);
+    r.ldc = M;
+    r.T = a.take<double>((size_t)cdiv(M, b) * b * b);
+    r.ldband = 2 * b + 1;
+    r.band = a.take<double>((size_t)r.ldband * M);
+    int32_t* sync = a.take<int32_t>(M + 8);
+    int32_t* err = a.take<int32_t>(1);
+    Arena sa;
+    sa.cap = sy2sb_workspace(M, b);
+    sa.base = a.take<char>(sa.cap);
+    copy_matrix(M, M, C, ldc, r.C, M, s);
+    sy2sb(r, sa, s);
+    BulgeChase c;
+    c.n = M; c.b = b; c.band = r.band; c.ldband = r.ldband; c.d = d;
+    double* e_or_dummy = e ? e : r.T;  // e unused for M = 1
+    c.e = e_or_dummy;
+    c.V = nullptr; c.tau = nullptr; c.kmax = M > 1 ? cdiv(M - 1, b) : 1;
+    c.sync = sync; c.err = err;
+    sb2st(c, s);
+    return GEP_OK;
+  });
+}
+
+size_t gep_tridiag_eig_workspace_size(int64_t M, int job) {
+  if (M <= 0) return 256;
+  if (job == GEP_JOB_VALUES) return 4096;
+  return stedc_workspace(M) + 256;
+}
+
+int gep_tridiag_eig(int64_t M, const double* d, const double* e, double* lambda, double* Z,
+                    int64_t ldz, int job, void* workspace, size_t ws_bytes, int32_t* info,
+                    void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !d) return bad(2);
+  if (M > 1 && !e) return bad(3);
+  if (M > 0 && !lambda) return bad(4);
+  if (job != GEP_JOB_VALUES && job != GEP_JOB_VECTORS) return bad(7);
+  if (job == GEP_JOB_VECTORS) {
+    if (M > 0 && !Z) return bad(5);
+    if (ldz < m1) return bad(6);
+  }
+  if (!info) return bad(10);
+  if (ws_bytes < gep_tridiag_eig_workspace_size(M, job)) return GEP_ERR_WORKSPACE;
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(8);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    fill_i32(info, 1, 0, s);
+    if (M == 0) return GEP_OK;
+    Arena a;
+    a.base = (char*)workspace;
+    a.cap = ws_bytes;
+    if (job == GEP_JOB_VALUES) {
+      double* bounds = a.take<double>(2);
+      stebz_ws(M, d, e, lambda, bounds, s);
+    } else {
+      stedc(M, d, e, lambda, Z, ldz, info, a, s);
+    }
+    return GEP_OK;
+  });
+}
+
+int gep_profile_enable(int on) {
+  g_prof = on != 0;
+  return GEP_OK;
+}
+
+int gep_profile_read(double* ms, int n) {
+  if (!g_prof || !g_ev_recorded || !ms) return 0;
+  return guarded([&]() -> int {
+    GEP_HIP(hipEventSynchronize(g_ev[NPHASE]));
+    int k = 0;
+    for (int i = 0; i < NPHASE && i < n; ++i, ++k) {
+      float t = 0.0f;
+      GEP_HIP(hipEventElapsedTime(&t, g_ev[i], g_ev[i + 1]));
+      ms[i] = t;
+    }
+    return k;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,216 @@
+// Cholesky factorisation B = L L^T and the triangular solves built on it.
+//
+// Recursive (blocked) formulations: every level splits the triangle in two halves
+// whose sizes are multiples of NB, so almost all flops land in large MFMA GEMMs.
+// The NB x NB diagonal blocks are factorised in one workgroup with the block held
+// in LDS (128 x 129 doubles = 132 KB of the 160 KB per CU), and their inverses are
+// formed there too; a solve against a diagonal block is then a small GEMM with
+// that inverse.
+#include "common.h"
+#include "internal.h"
+
+namespace gep {
+namespace {
+
+constexpr int NT = 256;
+constexpr int LDS_LD = NB + 1;
+
+// Factor the n x n (n <= NB) diagonal block in place (lower triangle; the upper
+// triangle of the block is set to zero) and write its inverse (lower, NB x NB
+// slot, zeros above the diagonal) to linv.  A non-positive pivot at local column
+// j records info = info_add + row0 + j + 1 (first failure wins) and the pivot is
+// replaced by 1 so that later steps stay finite.
+__global__ void __launch_bounds__(NT)
+potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict__ linv,
+                 int32_t* __restrict__ info, int64_t row0, int64_t info_add) {
+  extern __shared__ double S[];  // column-major, ld LDS_LD
+  double* tcol = S + (size_t)NB * LDS_LD;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx % n, j = idx / n;
+    S[i + j * LDS_LD] = (i >= j) ? a[i + j * lda] : 0.0;
+  }
+  __syncthreads();
+  // right-looking factorisation
+  for (int j = 0; j < n; ++j) {
+    const double piv = S[j + j * LDS_LD];
+    const bool ok = piv > 0.0;  // false for NaN too
+    const double ljj = ok ? sqrt(piv) : 1.0;
+    if (!ok && tid == 0 && info) atomicCAS(info, 0, (int32_t)(info_add + row0 + j + 1));
+    __syncthreads();
+    if (tid == 0) S[j + j * LDS_LD] = ljj;
+    const double rl = 1.0 / ljj;
+    for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LDS_LD] *= rl;
+    __syncthreads();
+    const int r = n - j - 1;
+    for (int idx = tid; idx < r * r; idx += NT) {
+      const int i = j + 1 + idx % r, k = j + 1 + idx / r;
+      if (i >= k) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * S[k + j * LDS_LD];
+    }
+    __syncthreads();
+  }
+  for (int idx = tid; idx < n * n; idx += NT) {
+    const int i = idx % n, j = idx / n;
+    a[i + j * lda] = (i >= j) ? S[i + j * LDS_LD] : 0.0;
+  }
+  // in-place inverse, columns right to left:
+  //   X(j,j) = 1/L(j,j);  X(j+1:, j) = -X(j+1:, j+1:) L(j+1:, j) X(j,j)
+  for (int j = n - 1; j >= 0; --j) {
+    __syncthreads();
+    for (int i = tid; i < n; i += NT) tcol[i] = S[i + j * LDS_LD];
+    __syncthreads();
+    const double xjj = 1.0 / tcol[j];
+    for (int i = j + 1 + tid; i < n; i += NT) {
+      double s = 0.0;
+      for (int k = j + 1; k <= i; ++k) s += S[i + k * LDS_LD] * tcol[k];
+      S[i + j * LDS_LD] = -s * xjj;
+    }
+    if (tid == 0) S[j + j * LDS_LD] = xjj;
+  }
+  __syncthreads();
+  for (int idx = tid; idx < NB * NB; idx += NT) {
+    const int i = idx % NB, j = idx / NB;
+    linv[i + j * NB] = (i < n && j < n && i >= j) ? S[i + j * LDS_LD] : 0.0;
+  }
+}
+
+int64_t split_point(int64_t n) {
+  const int64_t nblk = cdiv(n, NB);
+  return NB * ((nblk + 1) / 2);
+}
+
+const double* leaf_inv(const Tri& t) { return t.Linv + (t.off / NB) * (int64_t)NB * NB; }
+
+Tri sub(const Tri& t, int64_t k) {
+  Tri s = t;
+  s.L = t.L + k + k * t.ld;
+  s.off = t.off + k;
+  return s;
+}
+
+}  // namespace
+
+size_t potrf_leaf_lds() { return sizeof(double) * ((size_t)NB * LDS_LD + NB); }
+
+void potrf_leaf(int64_t n, double* a, int64_t lda, double* linv_blk, int32_t* info, int64_t row0,
+                int64_t info_add, hipStream_t s) {
+  static bool attr_set = false;
+  if (!attr_set) {
+    GEP_HIP(hipFuncSetAttribute((const void*)potrf_trtri_leaf,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)potrf_leaf_lds()));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(potrf_trtri_leaf, dim3(1), dim3(NT), potrf_leaf_lds(), s, (int)n, a, lda,
+                     linv_blk, info, row0, info_add);
+  GEP_LAUNCH_CHECK();
+}
+
+// X (n x ncols) <- L^{-1} X
+void trsm_lln(const Tri& t, int64_t n, double* X, int64_t ldx, int64_t ncols, double* tmp,
+              hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  if (n <= NB) {
+    Gemm g;
+    g.m = n; g.n = ncols; g.k = n;
+    g.A = leaf_inv(t); g.lda = NB; g.B = X; g.ldb = ldx; g.C = tmp; g.ldc = n;
+    gemm(g, s);
+    copy_matrix(n, ncols, tmp, n, X, ldx, s);
+    return;
+  }
+  const int64_t n1 = split_point(n);
+  trsm_lln(t, n1, X, ldx, ncols, tmp, s);
+  Gemm g;
+  g.m = n - n1; g.n = ncols; g.k = n1; g.alpha = -1.0; g.beta = 1.0;
+  g.A = t.L + n1; g.lda = t.ld; g.B = X; g.ldb = ldx; g.C = X + n1; g.ldc = ldx;
+  gemm(g, s);
+  trsm_lln(sub(t, n1), n - n1, X + n1, ldx, ncols, tmp, s);
+}
+
+// X (n x ncols) <- L^{-T} X
+void trsm_llt(const Tri& t, int64_t n, double* X, int64_t ldx, int64_t ncols, double* tmp,
+              hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  if (n <= NB) {
+    Gemm g;
+    g.transA = true;
+    g.m = n; g.n = ncols; g.k = n;
+    g.A = leaf_inv(t); g.lda = NB; g.B = X; g.ldb = ldx; g.C = tmp; g.ldc = n;
+    gemm(g, s);
+    copy_matrix(n, ncols, tmp, n, X, ldx, s);
+    return;
+  }
+  const int64_t n1 = split_point(n);
+  trsm_llt(sub(t, n1), n - n1, X + n1, ldx, ncols, tmp, s);
+  Gemm g;
+  g.transA = true;
+  g.m = n1; g.n = ncols; g.k = n - n1; g.alpha = -1.0; g.beta = 1.0;
+  g.A = t.L + n1; g.lda = t.ld; g.B = X + n1; g.ldb = ldx; g.C = X; g.ldc = ldx;
+  gemm(g, s);
+  trsm_llt(t, n1, X, ldx, ncols, tmp, s);
+}
+
+// X (nrows x n) <- X L^{-T}
+void trsm_rlt(const Tri& t, int64_t n, double* X, int64_t ldx, int64_t nrows, double* tmp,
+              hipStream_t s) {
+  if (n <= 0 || nrows <= 0) return;
+  if (n <= NB) {
+    Gemm g;
+    g.transB = true;
+    g.m = nrows; g.n = n; g.k = n;
+    g.A = X; g.lda = ldx; g.B = leaf_inv(t); g.ldb = NB; g.C = tmp; g.ldc = nrows;
+    gemm(g, s);
+    copy_matrix(nrows, n, tmp, nrows, X, ldx, s);
+    return;
+  }
+  const int64_t n1 = split_point(n);
+  trsm_rlt(t, n1, X, ldx, nrows, tmp, s);
+  Gemm g;
+  g.transB = true;
+  g.m = nrows; g.n = n - n1; g.k = n1; g.alpha = -1.0; g.beta = 1.0;
+  g.A = X; g.lda = ldx; g.B = t.L + n1; g.ldb = t.ld; g.C = X + n1 * ldx; g.ldc = ldx;
+  gemm(g, s);
+  trsm_rlt(sub(t, n1), n - n1, X + n1 * ldx, ldx, nrows, tmp, s);
+}
+
+// In place: lower triangle of a (n x n) -> L, Linv blocks written at linv + (off/NB)*NB*NB.
+void potrf_rec(double* a, int64_t lda, int64_t n, int64_t off, double* linv, int32_t* info,
+               int64_t info_add, double* tmp, hipStream_t s) {
+  if (n <= 0) return;
+  if (n <= NB) {
+    potrf_leaf(n, a, lda, linv + (off / NB) * (int64_t)NB * NB, info, off, info_add, s);
+    return;
+  }
+  const int64_t n1 = split_point(n);
+  potrf_rec(a, lda, n1, off, linv, info, info_add, tmp, s);
+  Tri t{a, lda, linv, off};
+  trsm_rlt(t, n1, a + n1, lda, n - n1, tmp, s);
+  Gemm g;
+  g.transB = true;
+  g.uplo = 1;
+  g.m = n - n1; g.n = n - n1; g.k = n1; g.alpha = -1.0; g.beta = 1.0;
+  g.A = a + n1; g.lda = lda; g.B = a + n1; g.ldb = lda; g.C = a + n1 + n1 * lda; g.ldc = lda;
+  gemm(g, s);
+  potrf_rec(a + n1 + n1 * lda, lda, n - n1, off + n1, linv, info, info_add, tmp, s);
+}
+
+// Lower triangle of X (n x n) <- lower triangle of X L^{-T}.  Only the lower
+// triangle of the result is formed; it reads only the lower triangle of X.
+void trsm_rlt_lower(const Tri& t, int64_t n, double* X, int64_t ldx, double* tmp, hipStream_t s) {
+  if (n <= 0) return;
+  if (n <= NB) {
+    trsm_rlt(t, n, X, ldx, n, tmp, s);
+    return;
+  }
+  const int64_t n1 = split_point(n);
+  trsm_rlt_lower(t, n1, X, ldx, tmp, s);
+  trsm_rlt(t, n1, X + n1, ldx, n - n1, tmp, s);
+  Gemm g;
+  g.transB = true;
+  g.uplo = 1;
+  g.m = n - n1; g.n = n - n1; g.k = n1; g.alpha = -1.0; g.beta = 1.0;
+  g.A = X + n1; g.lda = ldx; g.B = t.L + n1; g.ldb = t.ld; g.C = X + n1 + n1 * ldx; g.ldc = ldx;
+  gemm(g, s);
+  trsm_rlt_lower(sub(t, n1), n - n1, X + n1 + n1 * ldx, ldx, tmp, s);
+}
+
+}  // namespace gep

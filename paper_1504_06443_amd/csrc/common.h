@@ -1,0 +1,120 @@
+// Internal helpers shared by the HIP sources of libgep (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include <cstdio>
+
+namespace gep {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// Column-major element access.
+#define GEP_AT(p, i, j, ld) ((p)[(size_t)(j) * (size_t)(ld) + (size_t)(i)])
+
+struct HipError {
+  hipError_t err;
+  const char* what;
+};
+
+// Every HIP call on the host side goes through this; a failure is turned into a
+// C++ exception that the C ABI layer converts into GEP_ERR_HIP.
+#define GEP_HIP(call)                                         \
+  do {                                                        \
+    hipError_t e_ = (call);                                   \
+    if (e_ != hipSuccess) throw ::gep::HipError{e_, #call};   \
+  } while (0)
+
+#define GEP_LAUNCH_CHECK() GEP_HIP(hipGetLastError())
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+// Bump allocator over the caller's workspace.  Every region is 256-byte aligned.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  bool dry = false;  // size planning only: no pointer is dereferenced
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    size_t off = used;
+    used += bytes;
+    if (dry) return reinterpret_cast<T*>(off + 256);  // never dereferenced
+    if (used > cap) throw HipError{hipErrorOutOfMemory, "workspace too small"};
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// ---------------------------------------------------------------- GEMM
+// C = alpha * op(A) * op(B) + beta * C, FP64, column-major, on MFMA.
+//  uplo = 0: full C; uplo = 1: only the lower triangle (row >= col) of C is
+//  written and tiles strictly above the diagonal are skipped.
+//  symA: op(A) is a symmetric matrix of which only the lower triangle of A is
+//  stored (transA is ignored).
+struct Gemm {
+  bool transA = false, transB = false, symA = false;
+  int uplo = 0;
+  int64_t m = 0, n = 0, k = 0;
+  double alpha = 1.0, beta = 0.0;
+  const double* A = nullptr;
+  int64_t lda = 0;
+  const double* B = nullptr;
+  int64_t ldb = 0;
+  double* C = nullptr;
+  int64_t ldc = 0;
+  // Strided batch: problem z uses A + z*strideA etc.
+  int batch = 1;
+  int64_t strideA = 0, strideB = 0, strideC = 0;
+  // Optional scratch for splitting a long k loop over several workgroups (used
+  // when C has few tiles).  Needs splitk_work_elems(m, n, k) doubles.
+  double* work = nullptr;
+  size_t work_elems = 0;
+};
+void gemm(const Gemm& g, hipStream_t s);
+
+// A problem of a grouped launch, written to device memory by an earlier kernel.
+struct GemmDesc {
+  int64_t m, n, k;
+  double alpha, beta;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  int transA, transB;
+};
+// One launch for `count` problems; max_m / max_n bound every problem's size.
+void gemm_grouped(const GemmDesc* desc, int count, int64_t max_m, int64_t max_n, hipStream_t s);
+size_t splitk_work_elems(int64_t m, int64_t n, int64_t k);
+
+// Same contraction in FP32 storage and FP32 MFMA accumulation.
+struct GemmF {
+  bool transA = false, transB = false;
+  int uplo = 0;
+  int64_t m = 0, n = 0, k = 0;
+  float alpha = 1.0f, beta = 0.0f;
+  const float* A = nullptr;
+  int64_t lda = 0;
+  const float* B = nullptr;
+  int64_t ldb = 0;
+  float* C = nullptr;
+  int64_t ldc = 0;
+};
+void gemm_f32(const GemmF& g, hipStream_t s);
+
+// Small elementwise helpers (in misc.hip).
+void copy_matrix(int64_t m, int64_t n, const double* src, int64_t lds, double* dst, int64_t ldd,
+                 hipStream_t s);
+void symmetrize_from_lower(int64_t n, const double* src, int64_t lds, double* dst, int64_t ldd,
+                           hipStream_t s);
+void set_matrix(int64_t m, int64_t n, double offdiag, double diag, double* dst, int64_t ldd,
+                hipStream_t s);
+void zero_upper(int64_t n, double* dst, int64_t ldd, hipStream_t s);
+void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+void fill_f64(double* p, int64_t n, double v, hipStream_t s);
+
+}  // namespace gep

@@ -1,0 +1,98 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function the
+header declares, and rejects bad arguments on the host before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gep.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(gep_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1504_06443_amd import _binding
+    return _binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("gep_solve", "gep_workspace_size", "gep_status_string", "gep_reduce",
+              "gep_tridiag_eig", "gep_band_reduce", "gep_tridiagonalize"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_status_strings(lib):
+    assert lib.gep_status_string(0) == b"ok"
+    assert lib.gep_status_string(-1) == b"invalid argument"
+    assert lib.gep_status_string(-2) == b"workspace too small"
+
+
+def test_workspace_sizes_grow(lib):
+    s1 = lib.gep_workspace_size(100, 1, 0)
+    s2 = lib.gep_workspace_size(1000, 1, 0)
+    assert 0 < s1 < s2
+    assert lib.gep_workspace_size(1000, 0, 0) < s2
+    assert lib.gep_workspace_size(0, 1, 0) > 0
+
+
+P = ctypes.c_void_p
+FAKE = P(0x100000)  # never dereferenced: validation fails first
+
+
+def _solve(lib, M, lda=None, A=FAKE, B=FAKE, lam=FAKE, Y=FAKE, job=1, prec=0, ws=P(0x200000),
+           wsb=None, info=FAKE):
+    lda = M if lda is None else lda
+    wsb = lib.gep_workspace_size(max(M, 0), job, prec) if wsb is None else wsb
+    return lib.gep_solve(M, A, lda, B, max(M, 1), lam, Y, max(M, 1), job, prec, ws, wsb, info, None)
+
+
+@pytest.mark.parametrize("kwargs,arg", [
+    (dict(M=-1), 1),
+    (dict(M=10, A=P(0)), 2),
+    (dict(M=10, lda=9), 3),
+    (dict(M=10, B=P(0)), 4),
+    (dict(M=10, lam=P(0)), 6),
+    (dict(M=10, Y=P(0)), 7),
+    (dict(M=10, job=5), 9),
+    (dict(M=10, prec=7), 10),
+    (dict(M=10, ws=P(0x200010)), 11),
+    (dict(M=10, info=P(0)), 13),
+])
+def test_solve_rejects_bad_arguments(lib, kwargs, arg):
+    assert _solve(lib, **kwargs) == -1
+    assert lib.gep_last_bad_arg() == arg
+
+
+def test_solve_rejects_small_workspace(lib):
+    M = 50
+    need = lib.gep_workspace_size(M, 1, 0)
+    assert _solve(lib, M, wsb=need - 1) == -2
+
+
+def test_values_job_allows_null_Y(lib):
+    # argument checks pass; the call then fails only at the workspace check
+    M = 50
+    need = lib.gep_workspace_size(M, 0, 0)
+    assert _solve(lib, M, Y=P(0), job=0, wsb=need - 1) == -2
+
+
+def test_phase_entry_points_validate(lib):
+    assert lib.gep_reduce(-1, FAKE, 1, FAKE, 1, FAKE, 1, FAKE, 1, FAKE, 10, FAKE, None) == -1
+    assert lib.gep_last_bad_arg() == 1
+    assert lib.gep_tridiag_eig(5, FAKE, FAKE, FAKE, FAKE, 4, 1, FAKE, 1 << 30, FAKE, None) == -1
+    assert lib.gep_last_bad_arg() == 6
+    assert lib.gep_band_reduce(5, FAKE, 5, 65, FAKE, 70, FAKE, 1 << 30, None) == -1
+    assert lib.gep_last_bad_arg() == 4

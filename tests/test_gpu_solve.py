@@ -1,0 +1,92 @@
+"""GPU parity of the whole FP64 solve (gep_solve) against the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import max_subspace_sine, say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+# |d lambda| / ||A||_1 for the FP64 path; invariants as fixed in the design notes.
+TOL_LAMBDA = 1e-11
+TOL_ORTH = 1e-12
+TOL_RES = 1e-12
+
+
+def _gep():
+    import paper_1504_06443_amd as gep
+    return gep
+
+
+def check_against_oracle(A, B, lam, Y, r=None):
+    if r is None:
+        r = oracle.solve(A, B)
+    n1 = r.norm1
+    M = A.shape[0]
+    assert np.all(np.diff(lam) >= 0)
+    err = np.abs(lam - r.lam).max() / n1
+    assert err <= TOL_LAMBDA, err
+    orth = np.abs(Y.T @ B @ Y - np.eye(M)).max()
+    assert orth <= TOL_ORTH, orth
+    res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+    assert res <= TOL_RES, res
+    worst = max_subspace_sine(Y, r.Y, B, r.lam, 1e-8 * n1)
+    assert worst <= 1e-11 * n1, worst
+    return err, orth, res
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 17, 64, 65, 100, 129, 255, 300, 600])
+def test_solve_small(gpu, M):
+    say(f"[solve] M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 500 + M)
+    lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    check_against_oracle(A, B, to_np(lam), to_np(Y))
+
+
+def test_solve_c1_workload(gpu):
+    """The 512 workload (decay length 8, seed 1)."""
+    say("[solve] m512 workload")
+    A, B = synth.workload("m512")
+    lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    check_against_oracle(A, B, to_np(lam), to_np(Y))
+
+
+def test_solve_values_only(gpu):
+    say("[solve] values only M=400")
+    A, B = synth.banded_pair(400, 7.0, 77)
+    lam, Y = _gep().solve(to_gpu(A), to_gpu(B), job="values")
+    assert Y is None
+    r = oracle.solve(A, B, vectors=False)
+    assert np.abs(to_np(lam) - r.lam).max() / r.norm1 <= TOL_LAMBDA
+
+
+def test_solve_toeplitz_closed_form(gpu):
+    say("[solve] toeplitz closed form")
+    M = 257
+    a, b, c, d = -2.0, 0.9, 1.5, 0.4
+    A, B = synth.toeplitz_tridiag(M, a, b), synth.toeplitz_tridiag(M, c, d)
+    lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    t = np.arange(1, M + 1) * np.pi / (M + 1)
+    exact = np.sort((a + 2 * b * np.cos(t)) / (c + 2 * d * np.cos(t)))
+    assert np.abs(to_np(lam) - exact).max() <= 1e-13 * 8
+
+
+def test_solve_degenerate_alpha_B(gpu):
+    say("[solve] A = alpha B")
+    M = 150
+    _, B = synth.banded_pair(M, 5.0, 78)
+    lam, Y = _gep().solve(to_gpu(-1.5 * B), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    assert np.abs(lam + 1.5).max() <= 1e-13 * 8
+    assert np.abs(Y.T @ B @ Y - np.eye(M)).max() <= TOL_ORTH
+
+
+def test_solve_indefinite_B_reports_info(gpu):
+    say("[solve] indefinite B")
+    import torch
+    M = 100
+    A, B = synth.banded_pair(M, 5.0, 79)
+    B[40, 40] = -1.0
+    with pytest.raises(torch.linalg.LinAlgError):
+        _gep().solve(to_gpu(A), to_gpu(B))
