@@ -128,6 +128,16 @@ int gep_tridiag_eig(int64_t M, const double* d, const double* e, double* lambda,
                     void* stream);
 
 /*
+ * Building block: C = alpha op(A) op(B) + beta C in FP64 on the matrix cores
+ * (the contraction every blocked step of the solver is made of).  op(X) = X or
+ * X^T (trans = 0 / 1); op(A) is m x k, op(B) k x n, C m x n, all column-major
+ * device pointers.  uplo = 1 writes only the lower triangle of C (m == n).
+ */
+int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, void* stream);
+
+/*
  * Per-phase timing of the last gep_solve on this process: when enabled,
  * gep_solve records HIP events around its phases on `stream`.
  * gep_profile_read synchronises on the last event and writes up to n phase times

@@ -55,6 +55,7 @@ SIGNATURES = {
     "gep_tridiagonalize": (INT, [I64, P, I64, INT, P, P, P, SZ, P]),
     "gep_tridiag_eig_workspace_size": (SZ, [I64, INT]),
     "gep_tridiag_eig": (INT, [I64, P, P, P, P, I64, INT, P, SZ, P, P]),
+    "gep_dgemm": (INT, [INT, INT, INT, I64, I64, I64, DBL, P, I64, P, I64, DBL, P, I64, P]),
     "gep_profile_enable": (INT, [INT]),
     "gep_profile_read": (INT, [P, INT]),
 }

@@ -137,6 +137,25 @@ def tridiag_eig(d: torch.Tensor, e: torch.Tensor, job="vectors", check_info=True
     return lam, (Zcm.t() if Zcm is not None else None)
 
 
+def dgemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, alpha=1.0, beta=0.0,
+          lower_only=False):
+    """C = alpha A B + beta C on libgep's FP64 MFMA GEMM (row-major torch views are
+    handled as transposed column-major operands)."""
+    m, k = A.shape
+    k2, n = B.shape
+    assert k == k2
+    A = A.contiguous()
+    B = B.contiguous()
+    if C is None:
+        C = torch.zeros((m, n), dtype=torch.float64, device=A.device)
+    assert C.is_contiguous()
+    # row-major C = A B  <=>  column-major C^T = B^T A^T
+    st = lib().gep_dgemm(0, 0, 1 if lower_only else 0, n, m, k, float(alpha), _ptr(B), max(n, 1),
+                         _ptr(A), max(k, 1), float(beta), _ptr(C), max(n, 1), _stream())
+    check(st, "gep_dgemm")
+    return C
+
+
 def profile_enable(on: bool = True) -> None:
     lib().gep_profile_enable(1 if on else 0)
 

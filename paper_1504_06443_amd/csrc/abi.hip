@@ -124,9 +124,8 @@ void carve(Plan& p, Arena& a, int64_t M, bool vectors) {
   p.sync = a.take<int32_t>(M + 8);
   p.err = a.take<int32_t>(1);
   if (vectors) {
-    const size_t nref = sb2st_reflector_count(M, p.b);
-    p.V2 = a.take<double>(nref * p.b);
-    p.tau2 = a.take<double>(nref);
+    p.V2 = a.take<double>(sb2st_block_storage(M, p.b));
+    p.tau2 = a.take<double>(sb2st_reflector_count(M, p.b));
   } else {
     p.V2 = p.tau2 = nullptr;
   }
@@ -476,6 +475,33 @@ int gep_tridiag_eig(int64_t M, const double* d, const double* e, double* lambda,
     } else {
       stedc(M, d, e, lambda, Z, ldz, info, a, s);
     }
+    return GEP_OK;
+  });
+}
+
+int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k, double alpha,
+              const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
+              int64_t ldc, void* stream) {
+  g_bad_arg = 0;
+  if (transA != 0 && transA != 1) return bad(1);
+  if (transB != 0 && transB != 1) return bad(2);
+  if (uplo != 0 && (uplo != 1 || m != n)) return bad(3);
+  if (m < 0) return bad(4);
+  if (n < 0) return bad(5);
+  if (k < 0) return bad(6);
+  const int64_t arows = transA ? k : m, brows = transB ? n : k;
+  if (m > 0 && k > 0 && !A) return bad(8);
+  if (lda < (arows > 1 ? arows : 1)) return bad(9);
+  if (n > 0 && k > 0 && !B) return bad(10);
+  if (ldb < (brows > 1 ? brows : 1)) return bad(11);
+  if (m > 0 && n > 0 && !C) return bad(13);
+  if (ldc < (m > 1 ? m : 1)) return bad(14);
+  return guarded([&]() -> int {
+    Gemm g;
+    g.transA = transA; g.transB = transB; g.uplo = uplo;
+    g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc;
+    gemm(g, (hipStream_t)stream);
     return GEP_OK;
   });
 }

@@ -10,12 +10,9 @@
 // R goes to the band; V (explicit: unit diagonal, zeros above) stays in the panel's
 // place for the back transformation, T is kept per panel.
 //
-// The panel QR is latency-bound: one launch per column.  Each launch owns row
-// slices of the panel in G workgroups: it applies the previous reflector to the
-// remaining columns and accumulates, for the next column x, |x|^2 and x^T P_j.
-// The last workgroup to finish (counter + device-scope fences) reduces the
-// partial sums and forms the next reflector, so no grid-wide barrier is needed.
-// All the O(n^2 b) work is in MFMA GEMMs.
+// The panel QR is latency-bound (one reduction per column); it runs as one
+// cooperative launch per panel with the panel held in LDS across the grid.  All
+// the O(n^2 b) work is in MFMA GEMMs.
 #include "common.h"
 #include "internal.h"
 
@@ -25,145 +22,168 @@ namespace {
 constexpr int NT = 256;
 constexpr int MAXB = 64;  // largest supported band width
 
-struct PanelState {
-  double beta[MAXB];   // R(c, c)
-  double tau[MAXB];
-  double scal[MAXB];   // 1 / (x0 - beta): scales x(c+1:) into v
-  double wv[MAXB];     // tau * v^T P_j for the current reflector
-  unsigned int counter;
-};
-
-// Partial sums: part[g * (MAXB + 1) + q]; q = 0 -> sum_{i>c} x_i^2, q = 1 + j -> sum_{i>=c} x_i P(i, j).
-__global__ void __launch_bounds__(NT)
-panel_step(int64_t n, int w, int kmax, int c, double* __restrict__ P, int64_t ld,
-           PanelState* __restrict__ st, double* __restrict__ part, int64_t rows_per) {
-  __shared__ double red[NT / 64][MAXB + 1];
-  __shared__ bool last;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per;
-  int64_t r1 = r0 + rows_per;
-  if (r1 > n) r1 = n;
-
-  // 1) apply reflector c-1 to columns c..w-1 (rows >= c-1) and store v_{c-1}
-  if (c > 0) {
-    const int p = c - 1;
-    const double scal = st->scal[p];
-    for (int64_t i = r0 + tid; i < r1; i += NT) {
-      if (i < p) continue;
-      double v;
-      if (i == p) {
-        v = 1.0;
-      } else {
-        v = P[i + (int64_t)p * ld] * scal;
-        P[i + (int64_t)p * ld] = v;
-      }
-      for (int j = c; j < w; ++j) P[i + (int64_t)j * ld] -= v * st->wv[j];
-    }
-  }
-  if (c >= kmax) return;
-
-  // 2) partial sums for column c
-  double acc[MAXB + 1];
-#pragma unroll
-  for (int q = 0; q <= MAXB; ++q) acc[q] = 0.0;
-  for (int64_t i = r0 + tid; i < r1; i += NT) {
-    if (i < c) continue;
-    const double x = P[i + (int64_t)c * ld];
-    if (i > c) acc[0] += x * x;
-#pragma unroll
-    for (int j = 0; j < MAXB; ++j)
-      if (j > c && j < w) acc[1 + j] += x * P[i + (int64_t)j * ld];
-  }
-  // wave reduction then workgroup reduction
-#pragma unroll
-  for (int q = 0; q <= MAXB; ++q) {
-    double v = acc[q];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (lane == 0) red[wave][q] = v;
-  }
-  __syncthreads();
-  if (tid <= MAXB) {
-    double v = 0.0;
-    for (int wv = 0; wv < NT / 64; ++wv) v += red[wv][tid];
-    part[(int64_t)blockIdx.x * (MAXB + 1) + tid] = v;
-  }
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) {
-    const unsigned int prev = atomicAdd(&st->counter, 1u);
-    last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-
-  // 3) last workgroup: reduce and form reflector c
-  __shared__ double tot[MAXB + 1];
-  if (tid <= MAXB) {
-    double v = 0.0;
-    for (unsigned int g = 0; g < gridDim.x; ++g) v += part[(int64_t)g * (MAXB + 1) + tid];
-    tot[tid] = v;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const double x0 = P[c + (int64_t)c * ld];
-    const double sigma = tot[0];
-    double beta, tau, scal;
-    if (sigma == 0.0) {
-      beta = x0;
-      tau = 0.0;
-      scal = 0.0;
-    } else {
-      const double mu = sqrt(x0 * x0 + sigma);
-      beta = (x0 >= 0.0) ? -mu : mu;
-      tau = (beta - x0) / beta;
-      scal = 1.0 / (x0 - beta);
-    }
-    st->beta[c] = beta;
-    st->tau[c] = tau;
-    st->scal[c] = scal;
-    st->counter = 0u;
-  }
-  __syncthreads();
-  if (tid < MAXB) {
-    const int j = tid;
-    double wvj = 0.0;
-    if (j > c && j < w) {
-      const double x0 = P[c + (int64_t)c * ld];
-      const double pcj = P[c + (int64_t)j * ld];
-      const double vtp = pcj + st->scal[c] * (tot[1 + j] - x0 * pcj);
-      wvj = st->tau[c] * vtp;
-    }
-    st->wv[j] = wvj;
-  }
-  __threadfence();
+// Band data shared between workgroups of one launch: agent-scope relaxed atomics
+// (coherent across XCDs, written through).
+__device__ inline double cld(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void cst(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// After the panel QR: move R (upper trapezoid of the first kmax rows) to the band,
-// replace it by the explicit V (unit diagonal, zeros above), zero the V columns
-// without a reflector, and publish tau.
-__global__ void panel_finish(int64_t n, int w, int kmax, double* __restrict__ P, int64_t ld,
-                             const PanelState* __restrict__ st, double* __restrict__ band,
-                             int64_t ldband, int64_t col0, int b, double* __restrict__ tau_out) {
-  const int c = blockIdx.x;  // one block per panel column
-  const int tid = threadIdx.x;
-  // R entries: rows i <= c, i < n
-  for (int i = tid; i <= c && i < n; i += blockDim.x) {
-    double r;
-    if (i == c && c < kmax) r = st->beta[c];
-    else r = P[i + (int64_t)c * ld];
-    band[(b + i - c) + (col0 + c) * ldband] = r;
+// Whole-panel QR in one cooperative launch.  Workgroup g keeps rows
+// [g*rows_per, (g+1)*rows_per) of the panel in LDS for the whole factorisation.
+// Column c: every workgroup forms partial sums (|x|^2 below row c, x^T P_j), the
+// grid meets at a barrier, every workgroup reduces all partials in the same order
+// (so all derive the identical reflector) and updates its slice.  Partials and the
+// top row are double buffered by column parity, so one barrier per column is
+// enough.  On exit: V explicit (unit diagonal, zeros above) in P, R in the band,
+// tau[0..w).
+struct PanelArgs {
+  int64_t n;
+  int w, kmax;
+  double* P;
+  int64_t ld;
+  double* part;     // [2][G][MAXB]
+  double* top;      // [2][MAXB]
+  unsigned* bar;    // barrier counter (zero on entry)
+  double* tau;
+  double* band;
+  int64_t ldband, col0;
+  int b;
+  int rows_per;
+  int32_t* err;
+  uint64_t timeout_ticks;
+};
+
+__device__ bool grid_barrier(const PanelArgs& a, unsigned target) {
+  __syncthreads();
+  __shared__ int ok;
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(a.bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t t0 = wall_clock64();
+    ok = 1;
+    while (__hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (wall_clock64() - t0 > a.timeout_ticks) {
+        __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  for (int64_t i = tid; i < n; i += blockDim.x) {
-    double v;
-    if (c >= kmax) v = 0.0;
-    else if (i < c) v = 0.0;
-    else if (i == c) v = 1.0;
-    else continue;  // already holds v
-    P[i + (int64_t)c * ld] = v;
+  return ok != 0;
+}
+
+__global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
+  extern __shared__ double Ps[];  // rows_per x (MAXB + 1), row-major
+  __shared__ double wv[MAXB];
+  __shared__ double scal_sh, beta_sh, tau_sh;
+  constexpr int LDP = MAXB + 1;
+  const int tid = threadIdx.x;
+  const int G = gridDim.x, g = blockIdx.x;
+  const int w = a.w;
+  const int64_t r0 = (int64_t)g * a.rows_per;
+  int nr = (int)((a.n - r0) < a.rows_per ? (a.n - r0) : a.rows_per);
+  if (nr < 0) nr = 0;
+  // load the slice
+  for (int j = 0; j < w; ++j)
+    for (int i = tid; i < nr; i += NT) Ps[i * LDP + j] = a.P[(r0 + i) + (int64_t)j * a.ld];
+  __syncthreads();
+  for (int c = 0; c < a.kmax; ++c) {
+    const int buf = c & 1;
+    double* part = a.part + (size_t)buf * G * MAXB;
+    double* top = a.top + buf * MAXB;
+    // partial sums: thread (q, lane4) sums rows lane4, lane4+4, ...
+    {
+      const int q = tid >> 2, sub = tid & 3;
+      double acc = 0.0;
+      if (q >= c && q < w) {
+        for (int i = sub; i < nr; i += 4) {
+          const int64_t gi = r0 + i;
+          if (gi < c || (q == c && gi == c)) continue;
+          acc += Ps[i * LDP + c] * Ps[i * LDP + q];
+        }
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (sub == 0 && q >= c && q < w) cst(&part[(size_t)g * MAXB + q], acc);
+    }
+    if (c >= r0 && c < r0 + nr) {
+      const int li = (int)(c - r0);
+      for (int q = c + tid; q < w; q += NT) cst(&top[q], Ps[li * LDP + q]);
+    }
+    if (!grid_barrier(a, (unsigned)(G * (c + 1)))) return;
+    // every workgroup reduces the partials in the same order
+    if (tid < MAXB) {
+      const int q = tid;
+      double tot = 0.0;
+      if (q >= c && q < w)
+        for (int gg = 0; gg < G; ++gg) tot += cld(&part[(size_t)gg * MAXB + q]);
+      wv[q] = tot;  // holds sums for now
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double x0 = cld(&top[c]);
+      const double sigma = wv[c];
+      double beta, tau, scal;
+      if (sigma == 0.0) {
+        beta = x0; tau = 0.0; scal = 0.0;
+      } else {
+        const double mu = sqrt(x0 * x0 + sigma);
+        beta = (x0 >= 0.0) ? -mu : mu;
+        tau = (beta - x0) / beta;
+        scal = 1.0 / (x0 - beta);
+      }
+      scal_sh = scal; beta_sh = beta; tau_sh = tau;
+    }
+    __syncthreads();
+    const double scal = scal_sh, tau = tau_sh;
+    double wvq = 0.0;
+    if (tid > c && tid < w) {
+      const double x0 = cld(&top[c]);
+      const double pcj = cld(&top[tid]);
+      wvq = tau * (pcj + scal * (wv[tid] - x0 * pcj));
+    }
+    __syncthreads();
+    if (tid < MAXB) wv[tid] = wvq;
+    __syncthreads();
+    // apply H_c to the slice, store v_c
+    for (int i = tid; i < nr; i += NT) {
+      const int64_t gi = r0 + i;
+      if (gi < c) continue;
+      double v;
+      if (gi == c) {
+        v = 1.0;
+        Ps[i * LDP + c] = beta_sh;
+      } else {
+        v = Ps[i * LDP + c] * scal;
+        Ps[i * LDP + c] = v;
+      }
+      for (int j = c + 1; j < w; ++j) Ps[i * LDP + j] -= v * wv[j];
+    }
+    if (g == 0 && tid == 0) a.tau[c] = tau;
+    __syncthreads();
   }
-  if (tid == 0) tau_out[c] = (c < kmax) ? st->tau[c] : 0.0;
+  if (g == 0)
+    for (int c = a.kmax + tid; c < w; c += NT) a.tau[c] = 0.0;
+  // write back: R to the band, explicit V to the panel
+  for (int j = 0; j < w; ++j) {
+    for (int i = tid; i < nr; i += NT) {
+      const int64_t gi = r0 + i;
+      const double x = Ps[i * LDP + j];
+      double v;
+      if (gi <= j || j >= a.kmax) {
+        if (gi <= j) a.band[(a.b + gi - j) + (a.col0 + j) * a.ldband] = x;  // R(gi, j)
+        v = (gi == j && j < a.kmax) ? 1.0 : 0.0;
+      } else {
+        v = x;
+      }
+      a.P[gi + (int64_t)j * a.ld] = v;
+    }
+  }
 }
 
 // Copy the lower triangle of the diagonal block [col0, col0 + w) into the band.
@@ -179,20 +199,29 @@ __global__ void diag_to_band(const double* __restrict__ C, int64_t ldc, int64_t 
 __global__ void form_t(int w, const double* __restrict__ G, const double* __restrict__ tau,
                        double* __restrict__ T) {
   __shared__ double Ts[MAXB][MAXB + 1];
+  __shared__ double Gs[MAXB][MAXB + 1];
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < w * w; idx += blockDim.x) Ts[idx % w][idx / w] = 0.0;
+  for (int j = tid >> 6; j < w; j += 4)
+    for (int i = tid & 63; i < w; i += 64) {
+      Gs[i][j] = G[i + j * w];
+      Ts[i][j] = 0.0;
+    }
   __syncthreads();
   for (int c = 0; c < w; ++c) {
     const double tc = tau[c];
-    if (tid < c) {
-      double s = 0.0;
-      for (int k = tid; k < c; ++k) s += Ts[tid][k] * G[k + c * w];
-      Ts[tid][c] = -tc * s;
-    }
+    // 4 threads per row of T(0:c, c)
+    const int row = tid >> 2, q = tid & 3;
+    double acc = 0.0;
+    if (row < c)
+      for (int k = row + q; k < c; k += 4) acc += Ts[row][k] * Gs[k][c];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (row < c && q == 0) Ts[row][c] = -tc * acc;
     if (tid == 0) Ts[c][c] = tc;
     __syncthreads();
   }
-  for (int idx = tid; idx < w * w; idx += blockDim.x) T[idx] = Ts[idx % w][idx / w];
+  for (int j = tid >> 6; j < w; j += 4)
+    for (int i = tid & 63; i < w; i += 64) T[i + j * w] = Ts[i][j];
 }
 
 // VW = [V | W], WV = [W | V]  (n x 2w, ld n)
@@ -210,12 +239,23 @@ __global__ void pack_vw(int64_t n, int w, const double* __restrict__ V, int64_t 
   WV[i + (int64_t)(w + c) * n] = v;
 }
 
-int panel_blocks(int64_t n) {
-  // aim for ~256-row slices, at most 512 workgroups
-  int64_t g = cdiv(n, 256);
-  if (g > 512) g = 512;
-  if (g < 1) g = 1;
-  return (int)g;
+size_t panel_lds() { return sizeof(double) * 256 * (MAXB + 1); }
+
+// Largest grid of panel_qr_coop whose workgroups are all resident at once.
+int coop_blocks() {
+  static int cached = 0;
+  if (cached == 0) {
+    int dev = 0, cus = 0, per = 0;
+    GEP_HIP(hipGetDevice(&dev));
+    GEP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GEP_HIP(hipFuncSetAttribute((const void*)panel_qr_coop,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_lds()));
+    GEP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)panel_qr_coop, NT,
+                                                         panel_lds()));
+    cached = cus * (per > 0 ? per : 1);
+    if (cached > 512) cached = 512;
+  }
+  return cached;
 }
 
 }  // namespace
@@ -227,8 +267,8 @@ size_t sy2sb_workspace(int64_t n, int b) {
   e += 4 * nb;               // VW, WV
   e += 4 * (size_t)b * b;    // G, Y, Ws, tau
   e += splitk_work_elems(b, b, n) + 64;
-  e += 512 * (MAXB + 1);     // partials
-  return e * sizeof(double) + sizeof(PanelState) + 16 * 256;
+  e += 2 * 512 * MAXB + 2 * MAXB;  // partials, top row
+  return e * sizeof(double) + (cdiv(n, b) + 1) * sizeof(unsigned) + 16 * 256;
 }
 
 void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
@@ -245,10 +285,20 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
   double* tau = ws.take<double>((size_t)b);
   const size_t skw = splitk_work_elems(b, b, N) + 64;
   double* skbuf = ws.take<double>(skw);
-  double* part = ws.take<double>(512 * (MAXB + 1));
-  PanelState* st = ws.take<PanelState>(1);
-  GEP_HIP(hipMemsetAsync(st, 0, sizeof(PanelState), s));
+  double* part = ws.take<double>(2 * 512 * MAXB);
+  double* top = ws.take<double>(2 * MAXB);
+  const int64_t npanels = cdiv(N, b);
+  unsigned* bar = ws.take<unsigned>(npanels + 1);
+  int32_t* err = ws.take<int32_t>(1);
+  fill_i32((int32_t*)bar, npanels + 1, 0, s);
+  fill_i32(err, 1, 0, s);
   fill_f64(r.band, r.ldband * N, 0.0, s);
+  const int coop_max = coop_blocks();
+  int dev = 0, rate_khz = 0;
+  GEP_HIP(hipGetDevice(&dev));
+  GEP_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+  if (rate_khz <= 0) rate_khz = 100000;
+  const uint64_t timeout_ticks = (uint64_t)rate_khz * 1000ull * 10ull;
 
   for (int64_t col0 = 0; col0 < N; col0 += b) {
     const int w = (int)((N - col0) < b ? (N - col0) : b);
@@ -260,16 +310,18 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
     if (n <= 0) break;
     double* P = r.C + p0 + col0 * r.ldc;
     const int kmax = (int)(n < w ? n : w);
-    const int gb = panel_blocks(n);
-    const int64_t rows_per = cdiv(n, gb);
-    for (int c = 0; c <= kmax; ++c) {
-      hipLaunchKernelGGL(panel_step, dim3(gb), dim3(NT), 0, s, n, w, kmax, c, P, r.ldc, st, part,
-                         rows_per);
-      GEP_LAUNCH_CHECK();
+    {
+      const int G = (int)cdiv(n, 256) < coop_max ? (int)cdiv(n, 256) : coop_max;
+      PanelArgs pa;
+      pa.n = n; pa.w = w; pa.kmax = kmax; pa.P = P; pa.ld = r.ldc; pa.part = part; pa.top = top;
+      pa.bar = bar + (col0 / b); pa.tau = tau; pa.band = r.band; pa.ldband = r.ldband;
+      pa.col0 = col0; pa.b = b; pa.rows_per = (int)cdiv(n, G); pa.err = err;
+      pa.timeout_ticks = timeout_ticks;
+      if (pa.rows_per > 256) throw HipError{hipErrorInvalidValue, "panel too tall"};
+      void* args[] = {&pa};
+      GEP_HIP(hipLaunchCooperativeKernel((const void*)panel_qr_coop, dim3(G), dim3(NT), args,
+                                         panel_lds(), s));
     }
-    hipLaunchKernelGGL(panel_finish, dim3(w), dim3(256), 0, s, n, w, kmax, P, r.ldc,
-                       (const PanelState*)st, r.band, r.ldband, col0, b, tau);
-    GEP_LAUNCH_CHECK();
     double* T = r.T + (col0 / b) * (int64_t)b * b;
     {  // G = V^T V
       Gemm g;

@@ -32,14 +32,36 @@ namespace {
 constexpr int NT = 256;
 constexpr int MAXB = 64;
 constexpr int LDS_LD = MAXB + 1;
+// Q2 blocks: NBW consecutive sweeps at one position, stored as HP x NBW (row-major),
+// column c = reflector of sweep s0 + c shifted down by c rows.
+constexpr int NBW = 32;
+constexpr int HP = 96;   // >= MAXB + NBW - 1
 
 __device__ inline double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-// Householder for x (length L, in LDS): returns beta, tau; overwrites x by v
-// (v[0] = 1).  Called by all threads; uses wave 0 for the reduction.
+// Band data is shared between workgroups inside one launch, so every access to it
+// is an agent-scope relaxed atomic: loads see the latest value written by any XCD
+// and stores are written through, which leaves nothing dirty in L2 for the
+// release that publishes a sweep's progress.
+__device__ inline double cld(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void cst(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sum over groups of 4 consecutive lanes.
+__device__ inline double quad_sum(double v) {
+  v += __shfl_xor(v, 1, 64);
+  v += __shfl_xor(v, 2, 64);
+  return v;
+}
+
+// Householder for x (length L, in LDS): H x = beta e_1, H = I - tau v v^T,
+// v[0] = 1.  Overwrites x by v.  Wave 0 reduces; all threads return beta, tau.
 __device__ void house(int L, double* x, double* sh, double& beta_out, double& tau_out) {
   const int tid = threadIdx.x;
   if (tid < 64) {
@@ -62,8 +84,7 @@ __device__ void house(int L, double* x, double* sh, double& beta_out, double& ta
   }
   __syncthreads();
   const double scal = sh[2];
-  for (int i = 1 + tid; i < L; i += NT) x[i] *= scal;
-  __syncthreads();
+  if (tid >= 1 && tid < L) x[tid] *= scal;
   if (tid == 0) x[0] = 1.0;
   beta_out = sh[0];
   tau_out = sh[1];
@@ -71,13 +92,17 @@ __device__ void house(int L, double* x, double* sh, double& beta_out, double& ta
 }
 
 // D (L x L symmetric, full in LDS, ld LDS_LD) <- H D H, H = I - tau v v^T.
+// 4 threads per row for the matrix-vector product.
 __device__ void two_sided(int L, double* D, const double* v, double tau, double* p, double* sh) {
   const int tid = threadIdx.x;
   if (tau == 0.0) return;
-  if (tid < L) {
-    double s = 0.0;
-    for (int j = 0; j < L; ++j) s += D[tid + j * LDS_LD] * v[j];
-    p[tid] = tau * s;
+  {
+    const int row = tid >> 2, q = tid & 3;
+    double acc = 0.0;
+    if (row < L)
+      for (int j = q; j < L; j += 4) acc += D[row + j * LDS_LD] * v[j];
+    acc = quad_sum(acc);
+    if (row < L && q == 0) p[row] = tau * acc;
   }
   __syncthreads();
   if (tid < 64) {
@@ -88,11 +113,10 @@ __device__ void two_sided(int L, double* D, const double* v, double tau, double*
   }
   __syncthreads();
   const double a = sh[3];
-  if (tid < L) p[tid] -= a * v[tid];
-  __syncthreads();
   for (int idx = tid; idx < L * L; idx += NT) {
     const int i = idx % L, j = idx / L;
-    D[i + j * LDS_LD] -= v[i] * p[j] + p[i] * v[j];
+    const double pi = p[i] - a * v[i], pj = p[j] - a * v[j];
+    D[i + j * LDS_LD] -= v[i] * pj + pi * v[j];
   }
   __syncthreads();
 }
@@ -119,16 +143,21 @@ __device__ inline int64_t positions(int64_t n, int b, int64_t s) {
 
 __device__ bool wait_for(const ChaseArgs& a, int64_t s, int32_t need) {
   // returns false on error / timeout
+  // Poll with relaxed loads (an acquire load per poll would invalidate this XCD's
+  // L2 every time); one acquire fence once the flag is seen.
   const uint64_t t0 = wall_clock64();
   for (;;) {
-    const int32_t p = __hip_atomic_load(&a.progress[s], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (p >= need) return true;
+    const int32_t p = __hip_atomic_load(&a.progress[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (p >= need) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
     if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
     if (wall_clock64() - t0 > a.timeout_ticks) {
       __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
-    __builtin_amdgcn_s_sleep(2);
+    __builtin_amdgcn_s_sleep(1);
   }
 }
 
@@ -167,32 +196,42 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
       }
       __syncthreads();
       if (!ok_sh) return;
-      __threadfence();  // see the predecessor's band writes
       const int64_t r = s + 1 + k * b;           // first row of this position
-      int L = (int)((n - r) < b ? (n - r) : b);  // reflector length
-      double beta, tau;
+      const int L = (int)((n - r) < b ? (n - r) : b);  // reflector length
+      const int64_t c = r - b;                   // first column of the block left of D
+      // load D (rows/cols r.., symmetric from the lower band) and the column
+      // block to its left (column s for k = 0, the bulge block E otherwise)
+      for (int idx = tid; idx < L * L; idx += NT) {
+        const int i = idx % L, j = idx / L;
+        if (i >= j) {
+          const double x = cld(&band[(i - j) + (r + j) * ld]);
+          Ds[i + j * LDS_LD] = x;
+          Ds[j + i * LDS_LD] = x;
+        }
+      }
       if (k == 0) {
-        // x = column s, rows s+1 .. s+L
-        for (int i = tid; i < L; i += NT) v[i] = band[(1 + i) + s * ld];
-        __syncthreads();
-        house(L, v, sh, beta, tau);
-        if (tid == 0) band[1 + s * ld] = beta;
-        for (int i = 1 + tid; i < L; i += NT) band[(1 + i) + s * ld] = 0.0;
+        if (tid < L) v[tid] = cld(&band[(1 + tid) + s * ld]);
       } else {
-        // E = rows r..r+L-1, cols c..c+Lprev-1, c = r - b
-        const int64_t c = r - b;
         for (int idx = tid; idx < L * Lprev; idx += NT) {
           const int i = idx % L, j = idx / L;
-          Es[i + j * LDS_LD] = band[(b + i - j) + (c + j) * ld];
+          Es[i + j * LDS_LD] = cld(&band[(b + i - j) + (c + j) * ld]);
         }
-        __syncthreads();
+      }
+      __syncthreads();
+      double beta, tau;
+      if (k == 0) {
+        house(L, v, sh, beta, tau);
+        if (tid == 0) cst(&band[1 + s * ld], beta);
+        if (tid >= 1 && tid < L) cst(&band[(1 + tid) + s * ld], 0.0);
+      } else {
         // E <- E (I - tau_prev vprev vprev^T)
         if (tau_prev != 0.0) {
-          if (tid < L) {
-            double y = 0.0;
-            for (int j = 0; j < Lprev; ++j) y += Es[tid + j * LDS_LD] * vprev[j];
-            p[tid] = tau_prev * y;
-          }
+          const int row = tid >> 2, q = tid & 3;
+          double acc = 0.0;
+          if (row < L)
+            for (int j = q; j < Lprev; j += 4) acc += Es[row + j * LDS_LD] * vprev[j];
+          acc = quad_sum(acc);
+          if (row < L && q == 0) p[row] = tau_prev * acc;
           __syncthreads();
           for (int idx = tid; idx < L * Lprev; idx += NT) {
             const int i = idx % L, j = idx / L;
@@ -200,61 +239,54 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
           }
           __syncthreads();
         }
-        // reflector from column 0 of E
-        for (int i = tid; i < L; i += NT) v[i] = Es[i];
+        // reflector from column 0 of E, applied from the left to columns 1..
+        if (tid < L) v[tid] = Es[tid];
         __syncthreads();
         house(L, v, sh, beta, tau);
-        // E(:, 1:) <- H E(:, 1:)
         if (tau != 0.0) {
-          if (tid >= 1 && tid < Lprev) {
-            double u = 0.0;
-            for (int i = 0; i < L; ++i) u += v[i] * Es[i + tid * LDS_LD];
-            p[tid] = tau * u;
-          }
+          const int col = tid >> 2, q = tid & 3;
+          double acc = 0.0;
+          if (col >= 1 && col < Lprev)
+            for (int i = q; i < L; i += 4) acc += v[i] * Es[i + col * LDS_LD];
+          acc = quad_sum(acc);
+          if (col >= 1 && col < Lprev && q == 0) p[col] = tau * acc;
           __syncthreads();
           for (int idx = tid; idx < L * Lprev; idx += NT) {
             const int i = idx % L, j = idx / L;
             if (j >= 1) Es[i + j * LDS_LD] -= v[i] * p[j];
           }
-          __syncthreads();
         }
         if (tid == 0) Es[0] = beta;
-        for (int i = 1 + tid; i < L; i += NT) Es[i] = 0.0;
+        if (tid >= 1 && tid < L) Es[tid] = 0.0;
         __syncthreads();
         for (int idx = tid; idx < L * Lprev; idx += NT) {
           const int i = idx % L, j = idx / L;
-          band[(b + i - j) + (c + j) * ld] = Es[i + j * LDS_LD];
+          cst(&band[(b + i - j) + (c + j) * ld], Es[i + j * LDS_LD]);
         }
       }
       // diagonal block rows/cols r .. r+L-1 <- H D H
       if (tau != 0.0) {
-        for (int idx = tid; idx < L * L; idx += NT) {
-          const int i = idx % L, j = idx / L;
-          const int hi = i > j ? i : j, lo = i > j ? j : i;
-          Ds[i + j * LDS_LD] = band[(hi - lo) + (r + lo) * ld];
-        }
-        __syncthreads();
         two_sided(L, Ds, v, tau, p, sh);
         for (int idx = tid; idx < L * L; idx += NT) {
           const int i = idx % L, j = idx / L;
-          if (i >= j) band[(i - j) + (r + j) * ld] = Ds[i + j * LDS_LD];
+          if (i >= j) cst(&band[(i - j) + (r + j) * ld], Ds[i + j * LDS_LD]);
         }
       }
-      // store the reflector, keep it for the next position
+      // store the reflector in its Q2 block (consumed by a later kernel)
       if (a.V) {
-        double* vout = a.V + (s * a.kmax + k) * b;
-        for (int i = tid; i < b; i += NT) vout[i] = (i < L) ? v[i] : 0.0;
-        if (tid == 0) a.tau[s * a.kmax + k] = tau;
+        const int64_t j = s / NBW;
+        const int cc = (int)(s % NBW);
+        double* blk = a.V + (j * a.kmax + k) * (int64_t)(HP * NBW);
+        if (tid < L) cst(&blk[(cc + tid) * NBW + cc], v[tid]);
+        if (tid == 0) cst(&a.tau[s * a.kmax + k], tau);
       }
-      for (int i = tid; i < L; i += NT) vprev[i] = v[i];
+      if (tid < L) vprev[tid] = v[tid];
       tau_prev = tau;
       Lprev = L;
-      __threadfence();
       __syncthreads();
-      if (tid == 0) {
+      if (tid == 0)
         __hip_atomic_store(&a.progress[s], (int32_t)(k + 1), __ATOMIC_RELEASE,
                            __HIP_MEMORY_SCOPE_AGENT);
-      }
     }
   }
 }
@@ -268,9 +300,6 @@ __global__ void extract_tridiag(int64_t n, const double* __restrict__ band, int6
 }
 
 // ---------------------------------------------------------------- Q2 application
-constexpr int NBW = 32;   // sweeps per compact-WY block
-constexpr int SW = 32;    // columns of Z per workgroup
-constexpr int HMAX = MAXB + NBW - 1;
 
 struct Q2Args {
   int64_t n;
@@ -283,51 +312,42 @@ struct Q2Args {
   int64_t ldz, ncols;
 };
 
-// Column c of the block of group j at position k: reflector (s0 + c, k) shifted
-// down by c rows; zero if that reflector does not exist.
-__device__ inline void load_block_v(const Q2Args& a, int64_t s0, int64_t k, int H, double* Vs,
-                                    double* taus) {
-  const int b = a.b;
-  for (int idx = threadIdx.x; idx < H * NBW; idx += blockDim.x) {
-    const int i = idx % H, c = idx / H;
-    const int64_t s = s0 + c;
-    double v = 0.0;
-    if (s < a.nsweeps && k < positions(a.n, b, s) && i >= c && i - c < b)
-      v = a.V[(s * a.kmax + k) * b + (i - c)];
-    Vs[i + c * HMAX] = v;
-  }
-  for (int c = threadIdx.x; c < NBW; c += blockDim.x) {
-    const int64_t s = s0 + c;
-    taus[c] = (s < a.nsweeps && k < positions(a.n, b, s)) ? a.tau[s * a.kmax + k] : 0.0;
-  }
-}
-
+// T factor of every block (forward accumulation, H_{s0} ... H_{s0+NBW-1} =
+// I - V T V^T), stored transposed (T^T row-major == T column-major).
 __global__ void __launch_bounds__(NT) q2_form_t(Q2Args a) {
-  __shared__ double Vs[HMAX * NBW];
+  __shared__ double Vs[HP * (NBW + 1)];
   __shared__ double Gm[NBW][NBW + 1];
   __shared__ double Ts[NBW][NBW + 1];
   __shared__ double taus[NBW];
   const int64_t k = blockIdx.x, j = blockIdx.y;
   const int64_t s0 = j * NBW;
   if (k >= positions(a.n, a.b, s0)) return;
+  const double* blk = a.V + (j * a.kmax + k) * (int64_t)(HP * NBW);
   const int H = a.b + NBW - 1;
-  load_block_v(a, s0, k, H, Vs, taus);
+  for (int idx = threadIdx.x; idx < H * NBW; idx += NT)
+    Vs[(idx / NBW) * (NBW + 1) + idx % NBW] = blk[idx];
+  for (int c = threadIdx.x; c < NBW; c += NT) {
+    const int64_t s = s0 + c;
+    taus[c] = (s < a.nsweeps && k < positions(a.n, a.b, s)) ? a.tau[s * a.kmax + k] : 0.0;
+  }
   __syncthreads();
   for (int idx = threadIdx.x; idx < NBW * NBW; idx += NT) {
     const int c1 = idx % NBW, c2 = idx / NBW;
     double g = 0.0;
-    for (int i = 0; i < H; ++i) g += Vs[i + c1 * HMAX] * Vs[i + c2 * HMAX];
+    for (int i = 0; i < H; ++i) g += Vs[i * (NBW + 1) + c1] * Vs[i * (NBW + 1) + c2];
     Gm[c1][c2] = g;
     Ts[c1][c2] = 0.0;
   }
   __syncthreads();
   for (int c = 0; c < NBW; ++c) {
     const double tc = taus[c];
-    if ((int)threadIdx.x < c) {
-      double acc = 0.0;
-      for (int q = threadIdx.x; q < c; ++q) acc += Ts[threadIdx.x][q] * Gm[q][c];
-      Ts[threadIdx.x][c] = -tc * acc;
-    }
+    const int row = threadIdx.x >> 2, q = threadIdx.x & 3;
+    double acc = 0.0;
+    if (row < c)
+      for (int kk = row + q; kk < c; kk += 4) acc += Ts[row][kk] * Gm[kk][c];
+    acc += __shfl_xor(acc, 1, 64);
+    acc += __shfl_xor(acc, 2, 64);
+    if (row < c && q == 0) Ts[row][c] = -tc * acc;
     if (threadIdx.x == 0) Ts[c][c] = tc;
     __syncthreads();
   }
@@ -336,53 +356,196 @@ __global__ void __launch_bounds__(NT) q2_form_t(Q2Args a) {
 }
 
 // Z <- (I - V T V^T) Z for every block, groups from last to first, positions in
-// increasing order; one workgroup per strip of SW columns.
+// increasing order; one workgroup per strip of SW columns, wave w owning columns
+// [16w, 16w + 16) of the strip through all three products (W1 = V^T Z,
+// W2 = T W1, Z -= V W2), so the products of different waves never meet.  Inside
+// a group the blocks slide down by b rows: the strip's rows live in a circular
+// LDS window, and per block only b rows are written back and b new rows loaded.
+// The V / T / new-row loads of block k+1 are issued into registers before the
+// MFMAs of block k.
+constexpr int SWA = 64;             // columns per workgroup (4 waves x 16)
+constexpr int HB = 128;             // circular window rows (>= HP + b)
+constexpr int ZLD = SWA + 1;
+constexpr int VLD = NBW + 1;
+constexpr int PV = HP * NBW / NT;   // V doubles per thread
+constexpr int PT = NBW * NBW / NT;  // T doubles per thread
+constexpr int PZ = MAXB * SWA / NT; // new-row doubles per thread
+
+struct Prefetch {
+  double v[PV], t[PT], z[PZ];
+};
+
+__device__ inline void fetch_vt(const Q2Args& a, int64_t j, int64_t k, Prefetch& f) {
+  const double* blk = a.V + (j * a.kmax + k) * (int64_t)(HP * NBW);
+  const double* Tg = a.T + (j * a.kmax + k) * NBW * NBW;
+#pragma unroll
+  for (int i = 0; i < PV; ++i) f.v[i] = blk[threadIdx.x + NT * i];
+#pragma unroll
+  for (int i = 0; i < PT; ++i) f.t[i] = Tg[threadIdx.x + NT * i];
+}
+
+// rows [lo, hi) relative to base (hi - lo <= MAXB); thread t: row t & 63,
+// columns (t >> 6) + 4 i.
+__device__ inline void fetch_rows(const Q2Args& a, int64_t base, int64_t lo, int64_t hi,
+                                  int64_t c0, int ncol, Prefetch& f) {
+  const int r = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < PZ; ++i) {
+    const int c = (threadIdx.x >> 6) + 4 * i;
+    f.z[i] = (lo + r < hi && c < ncol) ? a.Z[(base + lo + r) + (c0 + c) * a.ldz] : 0.0;
+  }
+}
+
+__device__ inline void commit_vt(const Prefetch& f, double* Vs, double* Tt) {
+#pragma unroll
+  for (int i = 0; i < PV; ++i) {
+    const int idx = threadIdx.x + NT * i;
+    Vs[(idx >> 5) * VLD + (idx & 31)] = f.v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = threadIdx.x + NT * i;
+    Tt[(idx >> 5) * VLD + (idx & 31)] = f.t[i];
+  }
+}
+
+__device__ inline void commit_rows(const Prefetch& f, int64_t lo, int64_t hi, double* Zs) {
+  const int r = threadIdx.x & 63;
+  if (lo + r >= hi) return;
+  const int slot = (int)((lo + r) & (HB - 1));
+#pragma unroll
+  for (int i = 0; i < PZ; ++i) Zs[slot * ZLD + (threadIdx.x >> 6) + 4 * i] = f.z[i];
+}
+
+__device__ inline void write_rows(const Q2Args& a, int64_t base, int64_t lo, int64_t hi, int64_t c0,
+                                  int ncol, const double* Zs) {
+  const int r = threadIdx.x & 63;
+  if (lo + r >= hi) return;
+  const int slot = (int)((lo + r) & (HB - 1));
+#pragma unroll
+  for (int i = 0; i < PZ; ++i) {
+    const int c = (threadIdx.x >> 6) + 4 * i;
+    if (c < ncol) a.Z[(base + lo + r) + (c0 + c) * a.ldz] = Zs[slot * ZLD + c];
+  }
+}
+
 __global__ void __launch_bounds__(NT) q2_apply(Q2Args a) {
-  __shared__ double Vs[HMAX * NBW];
-  __shared__ double Ts[NBW * NBW];
-  __shared__ double Zs[HMAX * (SW + 1)];
-  __shared__ double W1[NBW * (SW + 1)];
-  __shared__ double W2[NBW * (SW + 1)];
-  __shared__ double taus[NBW];
-  const int64_t c0 = (int64_t)blockIdx.x * SW;
-  const int ncol = (int)((a.ncols - c0) < SW ? (a.ncols - c0) : SW);
-  const int tid = threadIdx.x;
+  __shared__ double Vs[HP * VLD];        // V[row][c]
+  __shared__ double Tt[NBW * VLD];       // T^T[k][j]
+  __shared__ double Zs[HB * ZLD];        // Z[slot][col]
+  __shared__ double Wp[4][16 * VLD];     // per wave: W1^T then W2^T [col][c]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int b = a.b;
+  const int64_t c0 = (int64_t)blockIdx.x * SWA;
+  const int ncol = (int)((a.ncols - c0) < SWA ? (a.ncols - c0) : SWA);
+  const int Hfull = b + NBW - 1;
+  const int KS1 = (Hfull + 3) / 4;       // k-steps of W1 (rows beyond Hfull are zero in V)
+  for (int idx = tid; idx < HB * ZLD; idx += NT) Zs[idx] = 0.0;
+  double* W = Wp[wave];
+  Prefetch f;
+  if (a.ngroups > 0) fetch_vt(a, a.ngroups - 1, 0, f);
   for (int64_t j = a.ngroups - 1; j >= 0; --j) {
     const int64_t s0 = j * NBW;
-    const int64_t P0 = positions(a.n, a.b, s0);
+    const int64_t base = s0 + 1;
+    const int64_t nrel = a.n - base;
+    const int64_t P0 = positions(a.n, b, s0);
+    // first window of the group (not prefetched: the previous group has just been
+    // written back)
+    __syncthreads();
+    {
+      const int64_t hi = Hfull < nrel ? Hfull : nrel;
+      for (int64_t lo = 0; lo < hi; lo += MAXB) {
+        Prefetch g;
+        const int64_t h2 = (lo + MAXB) < hi ? (lo + MAXB) : hi;
+        fetch_rows(a, base, lo, h2, c0, ncol, g);
+        commit_rows(g, lo, h2, Zs);
+      }
+    }
     for (int64_t k = 0; k < P0; ++k) {
-      const int64_t r0 = s0 + 1 + k * a.b;
-      int H = a.b + NBW - 1;
-      if (r0 + H > a.n) H = (int)(a.n - r0);
-      load_block_v(a, s0, k, H, Vs, taus);
-      const double* Tg = a.T + (j * a.kmax + k) * NBW * NBW;
-      for (int idx = tid; idx < NBW * NBW; idx += NT) Ts[idx] = Tg[idx];
-      for (int idx = tid; idx < H * ncol; idx += NT) {
-        const int i = idx % H, c = idx / H;
-        Zs[i + c * HMAX] = a.Z[(r0 + i) + (c0 + c) * a.ldz];
+      const int64_t kb = k * b;
+      __syncthreads();  // the previous block's write-back frees the slots refilled here
+      commit_vt(f, Vs, Tt);
+      if (k > 0) {
+        int64_t lo = kb - b + Hfull, hi = kb + Hfull;
+        if (hi > nrel) hi = nrel;
+        commit_rows(f, lo, hi, Zs);
       }
       __syncthreads();
-      for (int idx = tid; idx < NBW * ncol; idx += NT) {
-        const int r = idx % NBW, c = idx / NBW;
-        double acc = 0.0;
-        for (int i = 0; i < H; ++i) acc += Vs[i + r * HMAX] * Zs[i + c * HMAX];
-        W1[r + c * NBW] = acc;
+      // prefetch block k+1 (or the next group's first block)
+      if (k + 1 < P0) {
+        fetch_vt(a, j, k + 1, f);
+        int64_t lo = kb + Hfull, hi = kb + b + Hfull;
+        if (hi > nrel) hi = nrel;
+        if (hi > lo) fetch_rows(a, base, lo, hi, c0, ncol, f);
+      } else if (j > 0) {
+        fetch_vt(a, j - 1, 0, f);
+      }
+      // W1^T (16 x NBW) for this wave's columns: two chains sharing the Z operand
+      v4d w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+      for (int ks = 0; ks < KS1; ++ks) {
+        const int row = ks * 4 + (lane >> 4);
+        const int slot = (int)((kb + row) & (HB - 1));
+        const double av = Zs[slot * ZLD + wave * 16 + (lane & 15)];
+        const double b0 = Vs[row * VLD + (lane & 15)];
+        const double b1 = Vs[row * VLD + 16 + (lane & 15)];
+        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, w0, 0, 0, 0);
+        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, w1, 0, 0, 0);
+      }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        W[((lane >> 4) + 4 * r) * VLD + (lane & 15)] = w0[r];
+        W[((lane >> 4) + 4 * r) * VLD + 16 + (lane & 15)] = w1[r];
       }
       __syncthreads();
-      for (int idx = tid; idx < NBW * ncol; idx += NT) {
-        const int r = idx % NBW, c = idx / NBW;
-        double acc = 0.0;
-        for (int q = r; q < NBW; ++q) acc += Ts[r + q * NBW] * W1[q + c * NBW];
-        W2[r + c * NBW] = acc;
+      // W2^T = W1^T T^T
+      v4d u0 = {0.0, 0.0, 0.0, 0.0}, u1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NBW / 4; ++ks) {
+        const int kk = ks * 4 + (lane >> 4);
+        const double av = W[(lane & 15) * VLD + kk];
+        const double b0 = Tt[kk * VLD + (lane & 15)];
+        const double b1 = Tt[kk * VLD + 16 + (lane & 15)];
+        u0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, u0, 0, 0, 0);
+        u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, u1, 0, 0, 0);
       }
       __syncthreads();
-      for (int idx = tid; idx < H * ncol; idx += NT) {
-        const int i = idx % H, c = idx / H;
-        double acc = 0.0;
-        for (int q = 0; q < NBW; ++q) acc += Vs[i + q * HMAX] * W2[q + c * NBW];
-        a.Z[(r0 + i) + (c0 + c) * a.ldz] = Zs[i + c * HMAX] - acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        W[((lane >> 4) + 4 * r) * VLD + (lane & 15)] = u0[r];
+        W[((lane >> 4) + 4 * r) * VLD + 16 + (lane & 15)] = u1[r];
       }
       __syncthreads();
+      // Z_w^T -= W2^T V^T : 6 row tiles, independent chains
+      v4d acc[HP / 16];
+#pragma unroll
+      for (int t = 0; t < HP / 16; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int ks = 0; ks < NBW / 4; ++ks) {
+        const int cc = ks * 4 + (lane >> 4);
+        const double av = W[(lane & 15) * VLD + cc];
+#pragma unroll
+        for (int t = 0; t < HP / 16; ++t) {
+          const double bv = Vs[(t * 16 + (lane & 15)) * VLD + cc];
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < HP / 16; ++t) {
+        const int slot = (int)((kb + t * 16 + (lane & 15)) & (HB - 1));
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Zs[slot * ZLD + wave * 16 + (lane >> 4) + 4 * r] -= acc[t][r];
+      }
+      __syncthreads();
+      // rows [kb, kb + b) are final for this group
+      {
+        int64_t hi = kb + b;
+        if (k + 1 == P0) hi = nrel;  // last block: the whole remaining window
+        if (hi > nrel) hi = nrel;
+        for (int64_t lo = kb; lo < hi; lo += MAXB) {
+          const int64_t h2 = (lo + MAXB) < hi ? (lo + MAXB) : hi;
+          write_rows(a, base, lo, h2, c0, ncol, Zs);
+        }
+      }
     }
   }
 }
@@ -407,7 +570,7 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
   a.T = ws.take<double>((size_t)a.ngroups * a.kmax * NBW * NBW);
   hipLaunchKernelGGL(q2_form_t, dim3((unsigned)a.kmax, (unsigned)a.ngroups), dim3(NT), 0, s, a);
   GEP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SW)), dim3(NT), 0, s, a);
+  hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
   GEP_LAUNCH_CHECK();
 }
 
@@ -416,10 +579,18 @@ size_t sb2st_reflector_count(int64_t n, int b) {
   return (size_t)(n > 0 ? n : 1) * (size_t)kmax;
 }
 
+size_t sb2st_block_storage(int64_t n, int b) {
+  const int64_t kmax = n > 1 ? cdiv(n - 1, b) : 1;
+  const int64_t nsweeps = n > 2 ? n - 2 : 0;
+  const int64_t ngroups = nsweeps > 0 ? cdiv(nsweeps, NBW) : 1;
+  return (size_t)ngroups * kmax * HP * NBW;
+}
+
 void sb2st(const BulgeChase& c, hipStream_t s) {
   const int64_t n = c.n;
   if (c.b > MAXB || c.b < 1) throw HipError{hipErrorInvalidValue, "band width"};
   const int64_t nsweeps = n > 2 ? n - 2 : 0;
+  if (c.V) fill_f64(c.V, (int64_t)sb2st_block_storage(n, c.b), 0.0, s);
   if (nsweeps > 0) {
     int32_t* progress = c.sync;
     int32_t* ticket = c.sync + n;

@@ -26,10 +26,8 @@ potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict_
   extern __shared__ double S[];  // column-major, ld LDS_LD
   double* tcol = S + (size_t)NB * LDS_LD;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < n * n; idx += NT) {
-    const int i = idx % n, j = idx / n;
-    S[i + j * LDS_LD] = (i >= j) ? a[i + j * lda] : 0.0;
-  }
+  for (int j = tid >> 7; j < n; j += NT / 128)
+    for (int i = tid & 127; i < n; i += 128) S[i + j * LDS_LD] = (i >= j) ? a[i + j * lda] : 0.0;
   __syncthreads();
   // right-looking factorisation
   for (int j = 0; j < n; ++j) {
@@ -42,17 +40,15 @@ potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict_
     const double rl = 1.0 / ljj;
     for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LDS_LD] *= rl;
     __syncthreads();
-    const int r = n - j - 1;
-    for (int idx = tid; idx < r * r; idx += NT) {
-      const int i = j + 1 + idx % r, k = j + 1 + idx / r;
-      if (i >= k) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * S[k + j * LDS_LD];
+    // trailing update of the lower triangle: 2 threads per column
+    for (int k = j + 1 + (tid >> 1); k < n; k += NT / 2) {
+      const double lkj = S[k + j * LDS_LD];
+      for (int i = k + (tid & 1); i < n; i += 2) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * lkj;
     }
     __syncthreads();
   }
-  for (int idx = tid; idx < n * n; idx += NT) {
-    const int i = idx % n, j = idx / n;
-    a[i + j * lda] = (i >= j) ? S[i + j * LDS_LD] : 0.0;
-  }
+  for (int j = tid >> 7; j < n; j += NT / 128)
+    for (int i = tid & 127; i < n; i += 128) a[i + j * lda] = (i >= j) ? S[i + j * LDS_LD] : 0.0;
   // in-place inverse, columns right to left:
   //   X(j,j) = 1/L(j,j);  X(j+1:, j) = -X(j+1:, j+1:) L(j+1:, j) X(j,j)
   for (int j = n - 1; j >= 0; --j) {
@@ -68,10 +64,9 @@ potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict_
     if (tid == 0) S[j + j * LDS_LD] = xjj;
   }
   __syncthreads();
-  for (int idx = tid; idx < NB * NB; idx += NT) {
-    const int i = idx % NB, j = idx / NB;
-    linv[i + j * NB] = (i < n && j < n && i >= j) ? S[i + j * LDS_LD] : 0.0;
-  }
+  for (int j = tid >> 7; j < NB; j += NT / 128)
+    for (int i = tid & 127; i < NB; i += 128)
+      linv[i + j * NB] = (i < n && j < n && i >= j) ? S[i + j * LDS_LD] : 0.0;
 }
 
 int64_t split_point(int64_t n) {

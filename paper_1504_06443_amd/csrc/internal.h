@@ -55,13 +55,14 @@ struct BulgeChase {
   int64_t ldband = 0;
   double* d = nullptr;     // out: diagonal (n)
   double* e = nullptr;     // out: subdiagonal (n-1)
-  double* V = nullptr;     // out: reflectors, sweep s, position k at V + (s*kmax + k)*b
+  double* V = nullptr;     // out: reflectors in Q2 block layout (sb2st_block_storage doubles)
   double* tau = nullptr;   // out: tau at tau[s*kmax + k]
   int64_t kmax = 0;        // reflector positions per sweep = ceil((n-1)/b)
   int32_t* sync = nullptr; // device scratch: progress flags (n + 8 ints)
   int32_t* err = nullptr;  // device: set to nonzero if a wait timed out
 };
 size_t sb2st_reflector_count(int64_t n, int b);
+size_t sb2st_block_storage(int64_t n, int b);
 void sb2st(const BulgeChase& c, hipStream_t s);
 // Z (n x ncols) <- Q2 Z with the bulge-chasing reflectors.
 size_t apply_q2_workspace(int64_t n, int b);
