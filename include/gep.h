@@ -85,6 +85,24 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
               size_t ws_bytes, int32_t* info, void* stream);
 
 /*
+ * Many independent problems of different orders in one call (the k-point-like
+ * batches of electronic-structure codes; the paper solves one problem per run).
+ * Arrays ending in _host are HOST arrays of length `batch` (orders, leading
+ * dimensions, and the device pointers of each instance's A, B, lambda, Y);
+ * info is a DEVICE int32 array [batch], one LAPACK-style code per instance.
+ * The instances are spread over worker streams forked from `stream` with events
+ * (largest first, each to the least loaded stream) and joined back into it, so
+ * the call can be captured in a HIP graph and replayed.  Workspace:
+ * gep_workspace_size_batched bytes for the same M_host list.
+ */
+size_t gep_workspace_size_batched(int batch, const int64_t* M_host, int job, int prec);
+int gep_solve_batched(int batch, const int64_t* M_host, const double* const* A_host,
+                      const int64_t* lda_host, const double* const* B_host,
+                      const int64_t* ldb_host, double* const* lambda_host, double* const* Y_host,
+                      const int64_t* ldy_host, int job, int prec, void* workspace, size_t ws_bytes,
+                      int32_t* info, void* stream);
+
+/*
  * Phase entry points (same conventions).  They expose the steps of gep_solve one
  * at a time so that each can be checked and timed on its own.
  *
@@ -126,6 +144,25 @@ size_t gep_tridiag_eig_workspace_size(int64_t M, int job);
 int gep_tridiag_eig(int64_t M, const double* d, const double* e, double* lambda, double* Z,
                     int64_t ldz, int job, void* workspace, size_t ws_bytes, int32_t* info,
                     void* stream);
+
+/*
+ * Adjoint of gep_solve for symmetric perturbations (reverse-mode derivative):
+ * given the solution (lambda, Y) and cotangents lambda_bar = dL/dlambda [M] and
+ * Y_bar = dL/dY [ldyb x M] (either may be NULL = zero), writes the symmetric
+ * gradients A_bar = dL/dA [ldab x M] and B_bar = dL/dB [ldbb x M] (full, both
+ * triangles).  Derived by differentiating A Y = B Y Lambda and Y^T B Y = I
+ * (section 3.1, Eq. 2): d lambda_k = y_k^T (dA - lambda_k dB) y_k, and the
+ * eigenvector term couples pairs (i, j) through 1 / (lambda_j - lambda_i).  That
+ * coupling is regularised near degeneracies: F_ij = D / (D^2 + eta^2) with
+ * D = lambda_j - lambda_i, and F_ij = 0 when |D| <= tau_c; it multiplies only the
+ * antisymmetric part of Y^T Y_bar, which is exact for losses invariant under
+ * rotations inside degenerate eigenspaces.  eta >= 0, tau_c >= 0.
+ */
+size_t gep_backward_workspace_size(int64_t M);
+int gep_backward(int64_t M, const double* lambda, const double* Y, int64_t ldy,
+                 const double* lambda_bar, const double* Y_bar, int64_t ldyb, double eta,
+                 double tau_c, double* A_bar, int64_t ldab, double* B_bar, int64_t ldbb,
+                 void* workspace, size_t ws_bytes, void* stream);
 
 /*
  * Building block: C = alpha op(A) op(B) + beta C in FP64 on the matrix cores

@@ -19,11 +19,11 @@ import os
 
 from ._binding import (GEPError, JOB_VALUES, JOB_VECTORS, PREC_FP64, PREC_MIXED, lib, lib_path,
                        workspace_size)
-from .api import (GEPFunction, band_reduce, backward, dgemm, reduce, solve, solve_batched,
+from .api import (BatchedSolver, GEPFunction, band_reduce, backward, dgemm, reduce, solve, solve_batched,
                   tridiag_eig, tridiagonalize, profile_enable, profile_read, PHASES)
 
 __all__ = [
     "GEPError", "JOB_VALUES", "JOB_VECTORS", "PREC_FP64", "PREC_MIXED", "lib", "lib_path",
-    "workspace_size", "GEPFunction", "band_reduce", "backward", "dgemm", "reduce", "solve",
+    "workspace_size", "BatchedSolver", "GEPFunction", "band_reduce", "backward", "dgemm", "reduce", "solve",
     "solve_batched", "tridiag_eig", "tridiagonalize", "profile_enable", "profile_read", "PHASES",
 ]

@@ -47,6 +47,8 @@ SIGNATURES = {
     "gep_version": (ctypes.c_char_p, []),
     "gep_workspace_size": (SZ, [I64, INT, INT]),
     "gep_solve": (INT, [I64, P, I64, P, I64, P, P, I64, INT, INT, P, SZ, P, P]),
+    "gep_workspace_size_batched": (SZ, [INT, P, INT, INT]),
+    "gep_solve_batched": (INT, [INT, P, P, P, P, P, P, P, P, INT, INT, P, SZ, P, P]),
     "gep_reduce_workspace_size": (SZ, [I64]),
     "gep_reduce": (INT, [I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P, P]),
     "gep_band_reduce_workspace_size": (SZ, [I64, INT]),
@@ -55,6 +57,8 @@ SIGNATURES = {
     "gep_tridiagonalize": (INT, [I64, P, I64, INT, P, P, P, SZ, P]),
     "gep_tridiag_eig_workspace_size": (SZ, [I64, INT]),
     "gep_tridiag_eig": (INT, [I64, P, P, P, P, I64, INT, P, SZ, P, P]),
+    "gep_backward_workspace_size": (SZ, [I64]),
+    "gep_backward": (INT, [I64, P, P, I64, P, P, I64, DBL, DBL, P, I64, P, I64, P, SZ, P]),
     "gep_dgemm": (INT, [INT, INT, INT, I64, I64, I64, DBL, P, I64, P, I64, DBL, P, I64, P]),
     "gep_profile_enable": (INT, [INT]),
     "gep_profile_read": (INT, [P, INT]),

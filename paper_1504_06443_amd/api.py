@@ -166,15 +166,104 @@ def profile_read() -> dict:
     return {PHASES[i]: buf[i] for i in range(n)}
 
 
-def solve_batched(As, Bs, job="vectors", prec="fp64", check_info=True):
-    raise NotImplementedError("gep_solve_batched is not built yet")
+class BatchedSolver:
+    """Solves a fixed list of problems (orders known up front) repeatedly.  Buffers
+    and the workspace are allocated once; run() enqueues gep_solve_batched on the
+    current stream (so it can be captured in a torch.cuda.CUDAGraph and replayed).
+    """
+
+    def __init__(self, sizes, job="vectors", device="cuda:0"):
+        self.sizes = [int(m) for m in sizes]
+        self.job = _JOBS[job]
+        dev = torch.device(device)
+        n = len(self.sizes)
+        self.A = [torch.zeros((m, m), dtype=torch.float64, device=dev) for m in self.sizes]
+        self.B = [torch.zeros((m, m), dtype=torch.float64, device=dev) for m in self.sizes]
+        self.lam = [torch.empty(m, dtype=torch.float64, device=dev) for m in self.sizes]
+        self.Ycm = ([torch.empty((m, m), dtype=torch.float64, device=dev) for m in self.sizes]
+                    if self.job == JOB_VECTORS else None)
+        I64A = ctypes.c_int64 * n
+        PA = ctypes.c_void_p * n
+        self._M = I64A(*self.sizes)
+        self._ld = I64A(*[max(m, 1) for m in self.sizes])
+        self._A = PA(*[t.data_ptr() for t in self.A])
+        self._B = PA(*[t.data_ptr() for t in self.B])
+        self._lam = PA(*[t.data_ptr() for t in self.lam])
+        self._Y = PA(*[t.data_ptr() for t in self.Ycm]) if self.Ycm is not None else PA()
+        self.ws_bytes = int(lib().gep_workspace_size_batched(n, self._M, self.job, PREC_FP64))
+        self.ws = _workspace(self.ws_bytes, dev)
+        self.info = torch.zeros(n, dtype=torch.int32, device=dev)
+
+    def load(self, As, Bs):
+        for dst, src in zip(self.A, As):
+            dst.copy_(src)
+        for dst, src in zip(self.B, Bs):
+            dst.copy_(src)
+
+    def run(self):
+        n = len(self.sizes)
+        st = lib().gep_solve_batched(n, self._M, self._A, self._ld, self._B, self._ld, self._lam,
+                                     self._Y, self._ld, self.job, PREC_FP64, _ptr(self.ws),
+                                     self.ws.numel(), _ptr(self.info), _stream())
+        check(st, "gep_solve_batched")
+
+    def results(self):
+        Ys = [Y.t() for Y in self.Ycm] if self.Ycm is not None else [None] * len(self.sizes)
+        return list(zip(self.lam, Ys))
 
 
-def backward(lam, Y, lam_bar, Y_bar, eta=0.0):
-    raise NotImplementedError("gep_backward is not built yet")
+def solve_batched(As, Bs, job="vectors", check_info=True):
+    """Solve A_i y = lambda B_i y for lists of square float64 CUDA tensors of
+    possibly different orders.  Returns a list of (lam, Y)."""
+    bs = BatchedSolver([A.shape[0] for A in As], job=job, device=As[0].device)
+    bs.load(As, Bs)
+    bs.run()
+    if check_info:
+        info = bs.info.cpu().tolist()
+        bad = [i for i, v in enumerate(info) if v != 0]
+        if bad:
+            raise torch.linalg.LinAlgError(f"gep_solve_batched: instances {bad} failed "
+                                           f"(info {[info[i] for i in bad]})")
+    return bs.results()
+
+
+def backward(lam, Y, lam_bar=None, Y_bar=None, eta=0.0, tau_c=0.0):
+    """Reverse-mode adjoint of solve(): symmetric (A_bar, B_bar) from the solution
+    (lam, Y) and the cotangents lam_bar = dL/dlam, Y_bar = dL/dY (None = zero)."""
+    lam = lam.contiguous()
+    M = lam.numel()
+    dev = lam.device
+    Ycm = Y.t().contiguous()  # column-major buffer of Y
+    Ybcm = Y_bar.t().contiguous() if Y_bar is not None else None
+    lb = lam_bar.contiguous() if lam_bar is not None else None
+    Ab = torch.empty((M, M), dtype=torch.float64, device=dev)
+    Bb = torch.empty((M, M), dtype=torch.float64, device=dev)
+    ws = _workspace(lib().gep_backward_workspace_size(M), dev)
+    st = lib().gep_backward(M, _ptr(lam), _ptr(Ycm), max(M, 1), _ptr(lb), _ptr(Ybcm), max(M, 1),
+                            float(eta), float(tau_c), _ptr(Ab), max(M, 1), _ptr(Bb), max(M, 1),
+                            _ptr(ws), ws.numel(), _stream())
+    check(st, "gep_backward")
+    return Ab, Bb  # symmetric: row- and column-major agree
 
 
 class GEPFunction(torch.autograd.Function):
+    """(A, B) -> (lam, Y) with the libgep adjoint as backward.  A and B are symmetric
+    float64 CUDA tensors; the gradients returned are the symmetric ones (the
+    derivative along symmetric perturbations), as torch.linalg.eigh does.
+    Degeneracy handling: eta (Lorentzian broadening) and tau_c (coupling cut-off)
+    are taken from GEPFunction.eta / GEPFunction.tau_c."""
+
+    eta = 0.0
+    tau_c = 0.0
+
     @staticmethod
     def forward(ctx, A, B):
-        raise NotImplementedError("gep_backward is not built yet")
+        lam, Y = solve(A, B)
+        ctx.save_for_backward(lam, Y)
+        return lam, Y
+
+    @staticmethod
+    def backward(ctx, lam_bar, Y_bar):
+        lam, Y = ctx.saved_tensors
+        Ab, Bb = backward(lam, Y, lam_bar, Y_bar, GEPFunction.eta, GEPFunction.tau_c)
+        return Ab, Bb

@@ -1,8 +1,10 @@
 // C ABI of libgep: argument validation on the host, workspace planning, and the
 // phase sequence of the solver (reducer, two-stage reduction, tridiagonal
 // eigensolver, back transformations).
+#include <algorithm>
 #include <cstring>
 #include <exception>
+#include <vector>
 
 #include "../../include/gep.h"
 #include "common.h"
@@ -99,7 +101,7 @@ size_t phase_scratch_bytes(int64_t M, int b, bool vectors) {
     s = s > stedc_workspace(M) ? s : stedc_workspace(M);
     const size_t q2 = apply_q2_workspace(M, b);
     s = s > q2 ? s : q2;
-    const size_t q1 = (size_t)2 * b * M * sizeof(double) + 1024;
+    const size_t q1 = apply_q1_workspace(M, M, b);
     s = s > q1 ? s : q1;
   }
   return s;
@@ -180,6 +182,142 @@ int guarded(F&& f) {
   }
 }
 
+// One generalized eigenproblem, enqueued on s (arguments already validated).
+// coop: launch the panel QR cooperatively (co-residency guaranteed by the runtime);
+// prof: record the phase events.
+void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+               double* lambda, double* Y, int64_t ldy, bool vectors, void* workspace,
+               size_t ws_bytes, int32_t* info, hipStream_t s, bool coop, bool prof_on) {
+  fill_i32(info, 1, 0, s);
+  if (M == 0) return;
+  Plan p;
+  Arena a;
+  a.base = (char*)workspace;
+  a.cap = ws_bytes;
+  carve(p, a, M, vectors);
+  Prof prof(s);
+  Prof* pp = prof_on ? &prof : nullptr;
+  if (pp) pp->mark(0);
+  reduce_steps(p, A, lda, B, ldb, info, s, pp);
+  {
+    Arena sa = scratch_arena(p);
+    BandReduction r = band_of(p);
+    r.coop = coop;
+    sy2sb(r, sa, s);
+  }
+  if (pp) pp->mark(3);
+  sb2st(chase_of(p), s);
+  if (pp) pp->mark(4);
+  if (!vectors) {
+    stebz_ws(M, p.d, p.e, lambda, p.bounds, s);
+    if (pp)
+      for (int i = 5; i <= 9; ++i) pp->mark(i);
+    return;
+  }
+  {
+    Arena sa = scratch_arena(p);
+    stedc(M, p.d, p.e, lambda, Y, ldy, info, sa, s);
+  }
+  if (pp) pp->mark(5);
+  {
+    Arena sa = scratch_arena(p);
+    apply_q2(chase_of(p), Y, ldy, M, sa, s);
+  }
+  if (pp) pp->mark(6);
+  {
+    Arena sa = scratch_arena(p);
+    apply_q1(band_of(p), Y, ldy, M, sa, s);
+  }
+  if (pp) pp->mark(7);
+  trsm_llt(Tri{p.L, M, p.Linv, 0}, M, Y, ldy, M, p.tmp, s);
+  if (pp) pp->mark(8);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
+  GEP_LAUNCH_CHECK();
+  if (pp) pp->mark(9);
+}
+
+// ---------------------------------------------------------------- batches
+// Instances run on NSTREAM worker streams forked from the caller's stream with
+// events (so the whole batch can be captured in one graph).  Longest-processing-
+// time order: instances sorted by M^3, each to the least loaded stream; every
+// stream owns one workspace slot sized for its largest instance.
+constexpr int NSTREAM = 16;
+
+struct BatchPlan {
+  std::vector<int> order;          // instance indices, largest first
+  std::vector<int> lane;           // instance -> stream
+  std::vector<size_t> slot_off;    // stream -> byte offset of its workspace slot
+  std::vector<size_t> slot_bytes;
+  size_t total = 0;
+};
+
+BatchPlan plan_batch(int batch, const int64_t* Mh, bool vectors) {
+  BatchPlan bp;
+  bp.order.resize(batch);
+  for (int i = 0; i < batch; ++i) bp.order[i] = i;
+  std::stable_sort(bp.order.begin(), bp.order.end(),
+                   [&](int a, int b) { return Mh[a] > Mh[b]; });
+  bp.lane.assign(batch, 0);
+  // Plain-launched panel grids spin at a barrier until all their workgroups are
+  // resident; keep the sum of concurrently possible grids within half the CUs.
+  int64_t gmax = 1;
+  for (int i = 0; i < batch; ++i) {
+    const int64_t g = cdiv(Mh[i] > 0 ? Mh[i] : 1, 256);
+    if (g > gmax) gmax = g;
+  }
+  int nlanes = (int)(128 / gmax);
+  if (nlanes < 1) nlanes = 1;
+  if (nlanes > NSTREAM) nlanes = NSTREAM;
+  std::vector<double> load(NSTREAM, 0.0);
+  std::vector<int64_t> maxm(NSTREAM, 0);
+  for (int i : bp.order) {
+    int best = 0;
+    for (int k = 1; k < nlanes; ++k)
+      if (load[k] < load[best]) best = k;
+    bp.lane[i] = best;
+    load[best] += (double)Mh[i] * Mh[i] * Mh[i];
+    if (Mh[i] > maxm[best]) maxm[best] = Mh[i];
+  }
+  bp.slot_off.assign(NSTREAM, 0);
+  bp.slot_bytes.assign(NSTREAM, 0);
+  size_t off = 0;
+  for (int k = 0; k < NSTREAM; ++k) {
+    size_t bytes = 0;
+    if (maxm[k] > 0) {
+      Plan p;
+      Arena a;
+      a.dry = true;
+      carve(p, a, maxm[k], vectors);
+      bytes = (a.used + 255) & ~size_t(255);
+    }
+    bp.slot_off[k] = off;
+    bp.slot_bytes[k] = bytes;
+    off += bytes;
+  }
+  bp.total = off + 256;
+  return bp;
+}
+
+struct Workers {
+  hipStream_t st[NSTREAM];
+  hipEvent_t fork;
+  hipEvent_t join[NSTREAM];
+  bool ok = false;
+};
+
+Workers& workers() {
+  static Workers w;
+  if (!w.ok) {
+    for (int k = 0; k < NSTREAM; ++k) {
+      GEP_HIP(hipStreamCreateWithFlags(&w.st[k], hipStreamNonBlocking));
+      GEP_HIP(hipEventCreateWithFlags(&w.join[k], hipEventDisableTiming));
+    }
+    GEP_HIP(hipEventCreateWithFlags(&w.fork, hipEventDisableTiming));
+    w.ok = true;
+  }
+  return w;
+}
+
 }  // namespace
 }  // namespace gep
 
@@ -236,49 +374,65 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
   if (ws_bytes < need) return GEP_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   return guarded([&]() -> int {
-    fill_i32(info, 1, 0, s);
-    if (M == 0) return GEP_OK;
-    const bool vectors = job == GEP_JOB_VECTORS;
-    Plan p;
-    Arena a;
-    a.base = (char*)workspace;
-    a.cap = ws_bytes;
-    carve(p, a, M, vectors);
-    Prof prof(s);
-    prof.mark(0);
-    reduce_steps(p, A, lda, B, ldb, info, s, &prof);
-    {
-      Arena sa = scratch_arena(p);
-      sy2sb(band_of(p), sa, s);
+    solve_one(M, A, lda, B, ldb, lambda, Y, ldy, job == GEP_JOB_VECTORS, workspace, ws_bytes, info,
+              s, true, true);
+    return GEP_OK;
+  });
+}
+
+size_t gep_workspace_size_batched(int batch, const int64_t* M_host, int job, int prec) {
+  (void)prec;
+  if (batch <= 0 || !M_host) return 256;
+  return plan_batch(batch, M_host, job == GEP_JOB_VECTORS).total;
+}
+
+int gep_solve_batched(int batch, const int64_t* M_host, const double* const* A_host,
+                      const int64_t* lda_host, const double* const* B_host,
+                      const int64_t* ldb_host, double* const* lambda_host, double* const* Y_host,
+                      const int64_t* ldy_host, int job, int prec, void* workspace, size_t ws_bytes,
+                      int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (batch < 0) return bad(1);
+  if (batch == 0) return GEP_OK;
+  if (!M_host) return bad(2);
+  if (!A_host) return bad(3);
+  if (!lda_host) return bad(4);
+  if (!B_host) return bad(5);
+  if (!ldb_host) return bad(6);
+  if (!lambda_host) return bad(7);
+  if (job != GEP_JOB_VALUES && job != GEP_JOB_VECTORS) return bad(10);
+  const bool vectors = job == GEP_JOB_VECTORS;
+  if (vectors && (!Y_host || !ldy_host)) return bad(8);
+  if (prec != GEP_PREC_FP64) return bad(11);
+  for (int i = 0; i < batch; ++i) {
+    const int64_t M = M_host[i];
+    const int64_t m1 = M > 1 ? M : 1;
+    if (M < 0) return bad(2);
+    if (M > 0 && (!A_host[i] || !B_host[i] || !lambda_host[i])) return bad(3);
+    if (lda_host[i] < m1) return bad(4);
+    if (ldb_host[i] < m1) return bad(6);
+    if (vectors && ((M > 0 && !Y_host[i]) || ldy_host[i] < m1)) return bad(9);
+  }
+  if (!info) return bad(14);
+  const BatchPlan bp = plan_batch(batch, M_host, vectors);
+  if (ws_bytes < bp.total) return GEP_ERR_WORKSPACE;
+  if (!workspace || ((uintptr_t)workspace & 255)) return bad(12);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    Workers& w = workers();
+    GEP_HIP(hipEventRecord(w.fork, s));
+    for (int k = 0; k < NSTREAM; ++k) GEP_HIP(hipStreamWaitEvent(w.st[k], w.fork, 0));
+    for (int i : bp.order) {
+      const int k = bp.lane[i];
+      solve_one(M_host[i], A_host[i], lda_host[i], B_host[i], ldb_host[i], lambda_host[i],
+                vectors ? Y_host[i] : nullptr, vectors ? ldy_host[i] : 1, vectors,
+                (char*)workspace + bp.slot_off[k], bp.slot_bytes[k], info + i, w.st[k], false,
+                false);
     }
-    prof.mark(3);
-    sb2st(chase_of(p), s);
-    prof.mark(4);
-    if (!vectors) {
-      stebz_ws(M, p.d, p.e, lambda, p.bounds, s);
-      for (int i = 5; i <= 9; ++i) prof.mark(i);
-      return GEP_OK;
+    for (int k = 0; k < NSTREAM; ++k) {
+      GEP_HIP(hipEventRecord(w.join[k], w.st[k]));
+      GEP_HIP(hipStreamWaitEvent(s, w.join[k], 0));
     }
-    {
-      Arena sa = scratch_arena(p);
-      stedc(M, p.d, p.e, lambda, Y, ldy, info, sa, s);
-    }
-    prof.mark(5);
-    {
-      Arena sa = scratch_arena(p);
-      apply_q2(chase_of(p), Y, ldy, M, sa, s);
-    }
-    prof.mark(6);
-    {
-      Arena sa = scratch_arena(p);
-      apply_q1(band_of(p), Y, ldy, M, sa, s);
-    }
-    prof.mark(7);
-    trsm_llt(Tri{p.L, M, p.Linv, 0}, M, Y, ldy, M, p.tmp, s);
-    prof.mark(8);
-    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
-    GEP_LAUNCH_CHECK();
-    prof.mark(9);
     return GEP_OK;
   });
 }
@@ -475,6 +629,42 @@ int gep_tridiag_eig(int64_t M, const double* d, const double* e, double* lambda,
     } else {
       stedc(M, d, e, lambda, Z, ldz, info, a, s);
     }
+    return GEP_OK;
+  });
+}
+
+size_t gep_backward_workspace_size(int64_t M) {
+  if (M <= 0) return 256;
+  return backward_workspace(M);
+}
+
+int gep_backward(int64_t M, const double* lambda, const double* Y, int64_t ldy,
+                 const double* lambda_bar, const double* Y_bar, int64_t ldyb, double eta,
+                 double tau_c, double* A_bar, int64_t ldab, double* B_bar, int64_t ldbb,
+                 void* workspace, size_t ws_bytes, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !lambda) return bad(2);
+  if (M > 0 && !Y) return bad(3);
+  if (ldy < m1) return bad(4);
+  if (Y_bar && ldyb < m1) return bad(7);
+  if (!(eta >= 0.0)) return bad(8);
+  if (!(tau_c >= 0.0)) return bad(9);
+  if (M > 0 && !A_bar) return bad(10);
+  if (ldab < m1) return bad(11);
+  if (M > 0 && !B_bar) return bad(12);
+  if (ldbb < m1) return bad(13);
+  if (ws_bytes < gep_backward_workspace_size(M)) return GEP_ERR_WORKSPACE;
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(14);
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    if (M == 0) return GEP_OK;
+    Arena a;
+    a.base = (char*)workspace;
+    a.cap = ws_bytes;
+    backward(M, lambda, Y, ldy, lambda_bar, Y_bar, ldyb, eta, tau_c, A_bar, ldab, B_bar, ldbb, a,
+             s);
     return GEP_OK;
   });
 }

@@ -318,9 +318,17 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
       pa.col0 = col0; pa.b = b; pa.rows_per = (int)cdiv(n, G); pa.err = err;
       pa.timeout_ticks = timeout_ticks;
       if (pa.rows_per > 256) throw HipError{hipErrorInvalidValue, "panel too tall"};
-      void* args[] = {&pa};
-      GEP_HIP(hipLaunchCooperativeKernel((const void*)panel_qr_coop, dim3(G), dim3(NT), args,
-                                         panel_lds(), s));
+      if (r.coop) {
+        void* args[] = {&pa};
+        GEP_HIP(hipLaunchCooperativeKernel((const void*)panel_qr_coop, dim3(G), dim3(NT), args,
+                                           panel_lds(), s));
+      } else {
+        // Batched solves: plain launch (graph-capturable).  Few workgroups (G <= 8
+        // for n <= 2048) per panel and at most 16 panels in flight, so the grid's
+        // workgroups always find free CUs; the barrier wait is bounded in time.
+        hipLaunchKernelGGL(panel_qr_coop, dim3(G), dim3(NT), panel_lds(), s, pa);
+        GEP_LAUNCH_CHECK();
+      }
     }
     double* T = r.T + (col0 / b) * (int64_t)b * b;
     {  // G = V^T V
@@ -382,40 +390,130 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
   }
 }
 
-// Z <- Q1 Z, Q1 = Q_0 Q_1 ... Q_last with Q_p = I - V_p T_p V_p^T:
-// apply the panels in reverse order.
+// Z <- Q1 Z, Q1 = Q_0 Q_1 ... Q_last with Q_p = I - V_p T_p V_p^T.  Panels are
+// applied in groups of QG consecutive panels, last group first: the product of a
+// group is one compact-WY block I - Vg Tg Vg^T with Vg = [V_p .. V_p+QG-1] stacked
+// from the group's first row (zeros above each panel's start) and
+//   Tg(blocks i<j) = -Tg(0:i, 0:i-block) Gg(.., j) T_j,  Gg = Vg^T Vg,
+// so the application is three large GEMMs (K = QG*b) per group.
+namespace {
+constexpr int QG = 4;
+
+// Vg (ng x QG*b, ld ng): panel i of the group starts at row i*b.
+__global__ void build_vg(int64_t ng, int b, int np, const double* __restrict__ C, int64_t ldc,
+                         int64_t col0, double* __restrict__ Vg) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ng) return;
+  const int c = blockIdx.y;        // column of Vg
+  const int pi = c / b;            // panel within the group
+  double v = 0.0;
+  if (pi < np) {
+    const int64_t r0 = (int64_t)pi * b;  // first row of this panel's V inside Vg
+    if (i >= r0) v = C[(col0 + b + i) + (col0 + c) * ldc];
+  }
+  Vg[i + (int64_t)c * ng] = v;
+}
+
+// Tg from the panel T's and Gg (one workgroup; QG*b <= 256).
+__global__ void __launch_bounds__(256) form_tg(int b, int np, const double* __restrict__ Tp,
+                                               const double* __restrict__ Gg, double* __restrict__ Tg) {
+  const int W = np * b;
+  const int tid = threadIdx.x;
+  __shared__ double X[(QG - 1) * 64 * 64];
+  for (int idx = tid; idx < W * W; idx += 256) Tg[idx] = 0.0;
+  __syncthreads();
+  for (int pi = 0; pi < np; ++pi) {
+    const double* T = Tp + (int64_t)pi * b * b;
+    for (int idx = tid; idx < b * b; idx += 256) {
+      const int r = idx % b, c = idx / b;
+      Tg[(pi * b + r) + (pi * b + c) * W] = T[idx];
+    }
+  }
+  __syncthreads();
+  for (int j = 1; j < np; ++j) {
+    const int jb = j * b;
+    const double* Tj = Tp + (int64_t)j * b * b;
+    // X = Gg(0:jb, block j) * T_j   (jb x b)
+    for (int idx = tid; idx < jb * b; idx += 256) {
+      const int r = idx % jb, c = idx / jb;
+      double acc = 0.0;
+      for (int q = 0; q <= c; ++q) acc += Gg[r + (jb + q) * W] * Tj[q + c * b];
+      X[r + c * jb] = acc;
+    }
+    __syncthreads();
+    // Tg(0:jb, block j) = -Tg(0:jb, 0:jb) X
+    for (int idx = tid; idx < jb * b; idx += 256) {
+      const int r = idx % jb, c = idx / jb;
+      double acc = 0.0;
+      for (int q = r; q < jb; ++q) acc += Tg[r + q * W] * X[q + c * jb];
+      Tg[r + (jb + c) * W] = -acc;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t apply_q1_workspace(int64_t n, int64_t ncols, int b) {
+  const int64_t W = (int64_t)QG * b;
+  size_t e = (size_t)n * W + 2 * (size_t)W * ncols + 2 * (size_t)W * W;
+  e += splitk_work_elems(W, W, n) + 64;
+  return e * sizeof(double) + 8 * 256;
+}
+
 void apply_q1(const BandReduction& r, double* Z, int64_t ldz, int64_t ncols, Arena& ws,
               hipStream_t s) {
   const int64_t N = r.n;
   const int b = r.b;
-  double* W1 = ws.take<double>((size_t)b * ncols);
-  double* W2 = ws.take<double>((size_t)b * ncols);
-  int64_t last = 0;
-  for (int64_t col0 = 0; col0 + b < N; col0 += b) last = col0;
   if (N <= b) return;
-  for (int64_t col0 = last; col0 >= 0; col0 -= b) {
+  const int64_t npan = cdiv(N - b, b);  // panels with rows below the band: col0 + b < N
+  const int64_t Wmax = (int64_t)QG * b;
+  double* Vg = ws.take<double>((size_t)N * Wmax);
+  double* W1 = ws.take<double>((size_t)Wmax * ncols);
+  double* W2 = ws.take<double>((size_t)Wmax * ncols);
+  double* Gg = ws.take<double>((size_t)Wmax * Wmax);
+  double* Tg = ws.take<double>((size_t)Wmax * Wmax);
+  const size_t skw = splitk_work_elems(Wmax, Wmax, N) + 64;
+  double* skbuf = ws.take<double>(skw);
+  const int64_t ngroups = cdiv(npan, QG);
+  for (int64_t gi = ngroups - 1; gi >= 0; --gi) {
+    const int64_t p_first = gi * QG;
+    const int np = (int)((npan - p_first) < QG ? (npan - p_first) : QG);
+    const int64_t col0 = p_first * b;
     const int64_t p0 = col0 + b;
-    const int64_t n = N - p0;
-    const int w = (int)((N - col0) < b ? (N - col0) : b);
-    const double* V = r.C + p0 + col0 * r.ldc;
-    const double* T = r.T + (col0 / b) * (int64_t)b * b;
+    const int64_t ng = N - p0;
+    const int64_t W = (int64_t)np * b;
+    hipLaunchKernelGGL(build_vg, dim3((unsigned)cdiv(ng, 256), (unsigned)W), dim3(256), 0, s, ng, b,
+                       np, (const double*)r.C, r.ldc, col0, Vg);
+    GEP_LAUNCH_CHECK();
     {
       Gemm g;
       g.transA = true;
-      g.m = w; g.n = ncols; g.k = n;
-      g.A = V; g.lda = r.ldc; g.B = Z + p0; g.ldb = ldz; g.C = W1; g.ldc = w;
+      g.m = W; g.n = W; g.k = ng;
+      g.A = Vg; g.lda = ng; g.B = Vg; g.ldb = ng; g.C = Gg; g.ldc = W;
+      g.work = skbuf; g.work_elems = skw;
+      gemm(g, s);
+    }
+    hipLaunchKernelGGL(form_tg, dim3(1), dim3(256), 0, s, b, np,
+                       (const double*)(r.T + (col0 / b) * (int64_t)b * b), (const double*)Gg, Tg);
+    GEP_LAUNCH_CHECK();
+    {
+      Gemm g;
+      g.transA = true;
+      g.m = W; g.n = ncols; g.k = ng;
+      g.A = Vg; g.lda = ng; g.B = Z + p0; g.ldb = ldz; g.C = W1; g.ldc = W;
       gemm(g, s);
     }
     {
       Gemm g;
-      g.m = w; g.n = ncols; g.k = w;
-      g.A = T; g.lda = w; g.B = W1; g.ldb = w; g.C = W2; g.ldc = w;
+      g.m = W; g.n = ncols; g.k = W;
+      g.A = Tg; g.lda = W; g.B = W1; g.ldb = W; g.C = W2; g.ldc = W;
       gemm(g, s);
     }
     {
       Gemm g;
-      g.m = n; g.n = ncols; g.k = w; g.alpha = -1.0; g.beta = 1.0;
-      g.A = V; g.lda = r.ldc; g.B = W2; g.ldb = w; g.C = Z + p0; g.ldc = ldz;
+      g.m = ng; g.n = ncols; g.k = W; g.alpha = -1.0; g.beta = 1.0;
+      g.A = Vg; g.lda = ng; g.B = W2; g.ldb = W; g.C = Z + p0; g.ldc = ldz;
       gemm(g, s);
     }
   }

@@ -113,10 +113,15 @@ __device__ void two_sided(int L, double* D, const double* v, double tau, double*
   }
   __syncthreads();
   const double a = sh[3];
-  for (int idx = tid; idx < L * L; idx += NT) {
-    const int i = idx % L, j = idx / L;
-    const double pi = p[i] - a * v[i], pj = p[j] - a * v[j];
-    D[i + j * LDS_LD] -= v[i] * pj + pi * v[j];
+  {
+    const int i = tid & 63;
+    if (i < L) {
+      const double vi = v[i], pi = p[i] - a * vi;
+      for (int j = tid >> 6; j < L; j += NT / 64) {
+        const double pj = p[j] - a * v[j];
+        D[i + j * LDS_LD] -= vi * pj + pi * v[j];
+      }
+    }
   }
   __syncthreads();
 }
@@ -201,20 +206,23 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
       const int64_t c = r - b;                   // first column of the block left of D
       // load D (rows/cols r.., symmetric from the lower band) and the column
       // block to its left (column s for k = 0, the bulge block E otherwise)
-      for (int idx = tid; idx < L * L; idx += NT) {
-        const int i = idx % L, j = idx / L;
-        if (i >= j) {
-          const double x = cld(&band[(i - j) + (r + j) * ld]);
-          Ds[i + j * LDS_LD] = x;
-          Ds[j + i * LDS_LD] = x;
-        }
+      {
+        const int i = tid & 63;
+        if (i < L)
+          for (int j = tid >> 6; j <= i; j += NT / 64) {
+            const double x = cld(&band[(i - j) + (r + j) * ld]);
+            Ds[i + j * LDS_LD] = x;
+            Ds[j + i * LDS_LD] = x;
+          }
       }
       if (k == 0) {
         if (tid < L) v[tid] = cld(&band[(1 + tid) + s * ld]);
       } else {
-        for (int idx = tid; idx < L * Lprev; idx += NT) {
-          const int i = idx % L, j = idx / L;
-          Es[i + j * LDS_LD] = cld(&band[(b + i - j) + (c + j) * ld]);
+        {
+          const int i = tid & 63;
+          if (i < L)
+            for (int j = tid >> 6; j < Lprev; j += NT / 64)
+              Es[i + j * LDS_LD] = cld(&band[(b + i - j) + (c + j) * ld]);
         }
       }
       __syncthreads();
@@ -233,9 +241,12 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
           acc = quad_sum(acc);
           if (row < L && q == 0) p[row] = tau_prev * acc;
           __syncthreads();
-          for (int idx = tid; idx < L * Lprev; idx += NT) {
-            const int i = idx % L, j = idx / L;
-            Es[i + j * LDS_LD] -= p[i] * vprev[j];
+          {
+            const int i = tid & 63;
+            if (i < L) {
+              const double pi = p[i];
+              for (int j = tid >> 6; j < Lprev; j += NT / 64) Es[i + j * LDS_LD] -= pi * vprev[j];
+            }
           }
           __syncthreads();
         }
@@ -251,25 +262,32 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
           acc = quad_sum(acc);
           if (col >= 1 && col < Lprev && q == 0) p[col] = tau * acc;
           __syncthreads();
-          for (int idx = tid; idx < L * Lprev; idx += NT) {
-            const int i = idx % L, j = idx / L;
-            if (j >= 1) Es[i + j * LDS_LD] -= v[i] * p[j];
+          {
+            const int i = tid & 63;
+            if (i < L) {
+              const double vi = v[i];
+              for (int j = 1 + (tid >> 6); j < Lprev; j += NT / 64) Es[i + j * LDS_LD] -= vi * p[j];
+            }
           }
         }
         if (tid == 0) Es[0] = beta;
         if (tid >= 1 && tid < L) Es[tid] = 0.0;
         __syncthreads();
-        for (int idx = tid; idx < L * Lprev; idx += NT) {
-          const int i = idx % L, j = idx / L;
-          cst(&band[(b + i - j) + (c + j) * ld], Es[i + j * LDS_LD]);
+        {
+          const int i = tid & 63;
+          if (i < L)
+            for (int j = tid >> 6; j < Lprev; j += NT / 64)
+              cst(&band[(b + i - j) + (c + j) * ld], Es[i + j * LDS_LD]);
         }
       }
       // diagonal block rows/cols r .. r+L-1 <- H D H
       if (tau != 0.0) {
         two_sided(L, Ds, v, tau, p, sh);
-        for (int idx = tid; idx < L * L; idx += NT) {
-          const int i = idx % L, j = idx / L;
-          if (i >= j) cst(&band[(i - j) + (r + j) * ld], Ds[i + j * LDS_LD]);
+        {
+          const int i = tid & 63;
+          if (i < L)
+            for (int j = tid >> 6; j <= i; j += NT / 64)
+              cst(&band[(i - j) + (r + j) * ld], Ds[i + j * LDS_LD]);
         }
       }
       // store the reflector in its Q2 block (consumed by a later kernel)

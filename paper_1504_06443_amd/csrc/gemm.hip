@@ -36,6 +36,7 @@ struct Params {
   int transA, transB, symA, uplo;
   int tiles_m, tiles_n;
   int64_t kchunk;  // > 0: batch index z sums k in [z*kchunk, (z+1)*kchunk) into C + z*sC
+  int vecA, vecB;  // operand base 16-byte aligned and leading dimension even
 };
 
 __device__ inline void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
@@ -151,14 +152,16 @@ __device__ inline void store_b(const Params& p, const double* rb, double* Bs) {
   }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool FAST>
 __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z);
 
-template <int BM, int BN, int BK>
+// FAST: every tile is interior, k is a multiple of BK and both operands are
+// 16-byte aligned with even leading dimensions (no bounds checks at all).
+template <int BM, int BN, int BK, bool FAST>
 __global__ void __launch_bounds__(NT) dgemm_kernel(Params p) {
   int tm, tn;
   tile_coords(p.tiles_m, p.tiles_n, tm, tn);
-  dgemm_tile<BM, BN, BK>(p, tm, tn, blockIdx.y);
+  dgemm_tile<BM, BN, BK, FAST>(p, tm, tn, blockIdx.y);
 }
 
 // Problems whose sizes live in device memory (written by an earlier kernel).
@@ -174,16 +177,98 @@ __global__ void __launch_bounds__(NT) dgemm_grouped_kernel(const GemmDesc* __res
   p.sA = p.sB = p.sC = 0;
   p.transA = d.transA; p.transB = d.transB; p.symA = 0; p.uplo = 0;
   p.tiles_m = tiles_m; p.tiles_n = tiles_n; p.kchunk = 0;
-  dgemm_tile<BM, BN, BK>(p, (int)blockIdx.x % tiles_m, (int)blockIdx.x / tiles_m, 0);
+  p.vecA = ((uintptr_t)d.A % 16 == 0) && (d.lda % 2 == 0);
+  p.vecB = ((uintptr_t)d.B % 16 == 0) && (d.ldb % 2 == 0);
+  dgemm_tile<BM, BN, BK, false>(p, (int)blockIdx.x % tiles_m, (int)blockIdx.x / tiles_m, 0);
 }
 
-template <int BM, int BN, int BK>
+// Interior tiles with a full k step and 16-byte aligned operands: unchecked
+// double2 loads.  ta selects op(A) read transposed (element (r, c) at A[c + r*lda]).
+template <int BM, int BN, int BK, int LDA_S, int LDB_S>
+struct FastIO {
+  static constexpr int PA2 = BM * BK / 2 / NT, PB2 = BN * BK / 2 / NT;
+  __device__ static inline void load(const Params& p, bool ta, const double* At, const double* Bt,
+                                     double* ra, double* rb) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PA2; ++i) {
+      const int idx = tid + NT * i;
+      double2 v;
+      if (!ta) {
+        const int rp = idx % (BM / 2), c = idx / (BM / 2);
+        v = *reinterpret_cast<const double2*>(At + 2 * rp + (int64_t)c * p.lda);
+      } else {
+        const int cp = idx % (BK / 2), r = idx / (BK / 2);
+        v = *reinterpret_cast<const double2*>(At + 2 * cp + (int64_t)r * p.lda);
+      }
+      ra[2 * i] = v.x;
+      ra[2 * i + 1] = v.y;
+    }
+#pragma unroll
+    for (int i = 0; i < PB2; ++i) {
+      const int idx = tid + NT * i;
+      double2 v;
+      if (!p.transB) {
+        const int kp = idx % (BK / 2), j = idx / (BK / 2);
+        v = *reinterpret_cast<const double2*>(Bt + 2 * kp + (int64_t)j * p.ldb);
+      } else {
+        const int jp = idx % (BN / 2), kk = idx / (BN / 2);
+        v = *reinterpret_cast<const double2*>(Bt + 2 * jp + (int64_t)kk * p.ldb);
+      }
+      rb[2 * i] = v.x;
+      rb[2 * i + 1] = v.y;
+    }
+  }
+  __device__ static inline void store(const Params& p, bool ta, const double* ra, const double* rb,
+                                      double* As, double* Bs) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < PA2; ++i) {
+      const int idx = tid + NT * i;
+      if (!ta) {
+        const int rp = idx % (BM / 2), c = idx / (BM / 2);
+        *reinterpret_cast<double2*>(As + c * LDA_S + 2 * rp) = double2{ra[2 * i], ra[2 * i + 1]};
+      } else {
+        const int cp = idx % (BK / 2), r = idx / (BK / 2);
+        As[(2 * cp) * LDA_S + r] = ra[2 * i];
+        As[(2 * cp + 1) * LDA_S + r] = ra[2 * i + 1];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PB2; ++i) {
+      const int idx = tid + NT * i;
+      if (!p.transB) {
+        const int kp = idx % (BK / 2), j = idx / (BK / 2);
+        Bs[(2 * kp) * LDB_S + j] = rb[2 * i];
+        Bs[(2 * kp + 1) * LDB_S + j] = rb[2 * i + 1];
+      } else {
+        const int jp = idx % (BN / 2), kk = idx / (BN / 2);
+        *reinterpret_cast<double2*>(Bs + kk * LDB_S + 2 * jp) = double2{rb[2 * i], rb[2 * i + 1]};
+      }
+    }
+  }
+};
+
+// Symmetric operand, k step straddling the diagonal, interior tile: element-wise
+// mirror select straight into LDS (no bounds checks).
+template <int BM, int BK, int LDA_S>
+__device__ inline void sym_diag_to_lds(const Params& p, const double* A, int64_t m0, int64_t k0,
+                                       double* As) {
+  for (int idx = threadIdx.x; idx < BM * BK; idx += NT) {
+    const int r = idx % BM, c = idx / BM;
+    const int64_t gr = m0 + r, gc = k0 + c;
+    As[c * LDA_S + r] = (gr >= gc) ? A[gr + gc * p.lda] : A[gc + gr * p.lda];
+  }
+}
+
+template <int BM, int BN, int BK, bool FAST>
 __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
   constexpr int PAD = 4;
   constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
   constexpr int WM = BM / 2, WN = BN / 2;  // per-wave sub-tile
   constexpr int FR = WM / 16, FC = WN / 16;
   constexpr int PA = BM * BK / NT, PB = BN * BK / NT;
+  using IO = FastIO<BM, BN, BK, LDA_S, LDB_S>;
   __shared__ double As[2][BK * LDA_S];
   __shared__ double Bs[2][BK * LDB_S];
 
@@ -211,21 +296,54 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
     for (int j = 0; j < FC; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
 
   const int64_t nk = (p.k + BK - 1) / BK;
+  const int64_t nk_full = p.k / BK;
+  const bool fast = FAST || (p.vecA && p.vecB && m0 + BM <= p.m && n0 + BN <= p.n);
+  // Per k step: 0 = fast, op(A) as stored; 1 = fast, op(A) read transposed;
+  // 2 = checked element-wise path.  A symmetric A (lower stored) is read as is on
+  // and below the diagonal and through its mirror above it.
+  auto mode_of = [&](int64_t kt) -> int {
+    if (!fast || kt >= nk_full) return 2;
+    if (!p.symA) return p.transA ? 1 : 0;
+    const int64_t k0 = kt * BK;
+    if (m0 >= k0 + BK - 1) return 0;
+    if (m0 + BM - 1 < k0) return 1;
+    return FAST ? 3 : 2;
+  };
+  auto a_ptr = [&](int mode, int64_t kt) -> const double* {
+    const int64_t k0 = kt * BK;
+    return mode == 1 ? A + k0 + m0 * p.lda : A + m0 + k0 * p.lda;
+  };
+  auto b_ptr = [&](int64_t kt) -> const double* {
+    const int64_t k0 = kt * BK;
+    return p.transB ? B + n0 + k0 * p.ldb : B + k0 + n0 * p.ldb;
+  };
+
   double ra[PA], rb[PB];
   if (nk > 0) {
-    load_a<BM, BK>(p, A, m0, 0, ra);
-    load_b<BN, BK>(p, B, 0, n0, rb);
-    store_a<BM, BK, LDA_S>(p, m0, 0, ra, As[0]);
-    store_b<BN, BK, LDB_S>(p, rb, Bs[0]);
+    const int mode = mode_of(0);
+    if (FAST && mode == 3) {
+      IO::load(p, false, a_ptr(0, 0), b_ptr(0), ra, rb);  // B part; A part replaced below
+      IO::store(p, false, ra, rb, As[0], Bs[0]);
+      __syncthreads();
+      sym_diag_to_lds<BM, BK, LDA_S>(p, A, m0, 0, As[0]);
+    } else if (FAST || mode != 2) {
+      IO::load(p, mode == 1, a_ptr(mode, 0), b_ptr(0), ra, rb);
+      IO::store(p, mode == 1, ra, rb, As[0], Bs[0]);
+    } else {
+      load_a<BM, BK>(p, A, m0, 0, ra);
+      load_b<BN, BK>(p, B, 0, n0, rb);
+      store_a<BM, BK, LDA_S>(p, m0, 0, ra, As[0]);
+      store_b<BN, BK, LDB_S>(p, rb, Bs[0]);
+    }
   }
   __syncthreads();
   for (int64_t kt = 0; kt < nk; ++kt) {
     const int buf = kt & 1;
     const bool more = kt + 1 < nk;
-    if (more) {
-      load_a<BM, BK>(p, A, m0, (kt + 1) * BK, ra);
-      load_b<BN, BK>(p, B, (kt + 1) * BK, n0, rb);
-    }
+    const int nmode = more ? mode_of(kt + 1) : 2;
+    // fast path: next k step prefetched into registers across the MFMAs
+    if (more && (FAST || nmode != 2))
+      IO::load(p, nmode == 1, a_ptr(nmode == 3 ? 0 : nmode, kt + 1), b_ptr(kt + 1), ra, rb);
     const double* as = As[buf];
     const double* bs = Bs[buf];
 #pragma unroll
@@ -243,8 +361,19 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);
     }
     if (more) {
-      store_a<BM, BK, LDA_S>(p, m0, (kt + 1) * BK, ra, As[buf ^ 1]);
-      store_b<BN, BK, LDB_S>(p, rb, Bs[buf ^ 1]);
+      if (FAST && nmode == 3) {
+        IO::store(p, false, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+        __syncthreads();
+        sym_diag_to_lds<BM, BK, LDA_S>(p, A, m0, (kt + 1) * BK, As[buf ^ 1]);
+      } else if (FAST || nmode != 2) {
+        IO::store(p, nmode == 1, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
+      } else {
+        // edge / unaligned / diagonal-straddling tile: checked loads, not prefetched
+        load_a<BM, BK>(p, A, m0, (kt + 1) * BK, ra);
+        load_b<BN, BK>(p, B, (kt + 1) * BK, n0, rb);
+        store_a<BM, BK, LDA_S>(p, m0, (kt + 1) * BK, ra, As[buf ^ 1]);
+        store_b<BN, BK, LDB_S>(p, rb, Bs[buf ^ 1]);
+      }
     }
     __syncthreads();
   }
@@ -271,7 +400,145 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
   }
 }
 
-template <int BM, int BN, int BK>
+constexpr int FAST_BK = 16;
+
+// Interior region: 128 x 128 tiles, BK = FAST_BK, k a multiple of BK, operands 16-byte
+// aligned with even leading dimensions, transposes fixed at compile time.  The
+// steady-state loop has no control flow besides the loop itself, which keeps the
+// accumulators resident in the matrix-core registers.
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+dgemm_fast_kernel(Params p) {
+  constexpr int BM = 128, BN = 128, BK = FAST_BK, PAD = 4;
+  constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
+  constexpr int WM = 64, WN = 64, FR = 4, FC = 4;
+  constexpr int PA2 = BM * BK / 2 / NT, PB2 = BN * BK / 2 / NT;
+  __shared__ double As[2][BK * LDA_S];
+  __shared__ double Bs[2][BK * LDB_S];
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  if (p.uplo == 1 && m0 + BM - 1 < n0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // per-thread global and LDS offsets of the staged double2 pieces
+  const double* Ap[PA2];
+  const double* Bp[PB2];
+  int as_off[PA2], bs_off[PB2];
+#pragma unroll
+  for (int i = 0; i < PA2; ++i) {
+    const int idx = tid + NT * i;
+    if (!TA) {
+      const int rp = idx % (BM / 2), c = idx / (BM / 2);
+      Ap[i] = p.A + m0 + 2 * rp + (int64_t)c * p.lda;
+      as_off[i] = c * LDA_S + 2 * rp;
+    } else {
+      const int cp = idx % (BK / 2), r = idx / (BK / 2);
+      Ap[i] = p.A + (m0 + r) * p.lda + 2 * cp;
+      as_off[i] = (2 * cp) * LDA_S + r;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PB2; ++i) {
+    const int idx = tid + NT * i;
+    if (!TB) {
+      const int kp = idx % (BK / 2), j = idx / (BK / 2);
+      Bp[i] = p.B + (n0 + j) * p.ldb + 2 * kp;
+      bs_off[i] = (2 * kp) * LDB_S + j;
+    } else {
+      const int jp = idx % (BN / 2), kk = idx / (BN / 2);
+      Bp[i] = p.B + n0 + 2 * jp + (int64_t)kk * p.ldb;
+      bs_off[i] = kk * LDB_S + 2 * jp;
+    }
+  }
+  const int64_t dA = TA ? BK : BK * p.lda;
+  const int64_t dB = TB ? BK * p.ldb : BK;
+
+  double2 ra[PA2], rb[PB2];
+#define GEP_FAST_GLOAD(kt_)                                                               \
+  {                                                                                       \
+    _Pragma("unroll") for (int i = 0; i < PA2; ++i) ra[i] =                               \
+        *reinterpret_cast<const double2*>(Ap[i] + (kt_) * dA);                            \
+    _Pragma("unroll") for (int i = 0; i < PB2; ++i) rb[i] =                               \
+        *reinterpret_cast<const double2*>(Bp[i] + (kt_) * dB);                            \
+  }
+#define GEP_FAST_LSTORE(buf_)                                                             \
+  {                                                                                       \
+    _Pragma("unroll") for (int i = 0; i < PA2; ++i) {                                     \
+      if (!TA) {                                                                          \
+        *reinterpret_cast<double2*>(&As[buf_][as_off[i]]) = ra[i];                        \
+      } else {                                                                            \
+        As[buf_][as_off[i]] = ra[i].x;                                                    \
+        As[buf_][as_off[i] + LDA_S] = ra[i].y;                                            \
+      }                                                                                   \
+    }                                                                                     \
+    _Pragma("unroll") for (int i = 0; i < PB2; ++i) {                                     \
+      if (!TB) {                                                                          \
+        Bs[buf_][bs_off[i]] = rb[i].x;                                                    \
+        Bs[buf_][bs_off[i] + LDB_S] = rb[i].y;                                            \
+      } else {                                                                            \
+        *reinterpret_cast<double2*>(&Bs[buf_][bs_off[i]]) = rb[i];                        \
+      }                                                                                   \
+    }                                                                                     \
+  }
+#define GEP_FAST_COMPUTE(buf_)                                                            \
+  {                                                                                       \
+    const double* as = As[buf_];                                                          \
+    const double* bs = Bs[buf_];                                                          \
+    _Pragma("unroll") for (int ks = 0; ks < BK / 4; ++ks) {                               \
+      const int krow = ks * 4 + (lane >> 4);                                              \
+      double af[FR], bf[FC];                                                              \
+      _Pragma("unroll") for (int i = 0; i < FR; ++i) af[i] =                              \
+          as[krow * LDA_S + wr * WM + i * 16 + (lane & 15)];                              \
+      _Pragma("unroll") for (int j = 0; j < FC; ++j) bf[j] =                              \
+          bs[krow * LDB_S + wc * WN + j * 16 + (lane & 15)];                              \
+      _Pragma("unroll") for (int i = 0; i < FR; ++i)                                      \
+          _Pragma("unroll") for (int j = 0; j < FC; ++j) acc[i][j] =                      \
+              __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);     \
+    }                                                                                     \
+  }
+
+  v4d acc[FR][FC];
+#pragma unroll
+  for (int i = 0; i < FR; ++i)
+#pragma unroll
+    for (int j = 0; j < FC; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  const int64_t nk = p.k / BK;
+  GEP_FAST_GLOAD(0)
+  GEP_FAST_LSTORE(0)
+  __syncthreads();
+  for (int64_t kt = 0; kt + 1 < nk; ++kt) {
+    GEP_FAST_GLOAD(kt + 1)
+    GEP_FAST_COMPUTE(kt & 1)
+    GEP_FAST_LSTORE((kt + 1) & 1)
+    __syncthreads();
+  }
+  GEP_FAST_COMPUTE((nk - 1) & 1)
+#undef GEP_FAST_GLOAD
+#undef GEP_FAST_LSTORE
+#undef GEP_FAST_COMPUTE
+
+#pragma unroll
+  for (int i = 0; i < FR; ++i) {
+    const int64_t row = m0 + wr * WM + i * 16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < FC; ++j) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t col = n0 + wc * WN + j * 16 + (lane >> 4) + 4 * r;
+        if (p.uplo == 1 && row < col) continue;
+        double* c = p.C + row + col * p.ldc;
+        double v = p.alpha * acc[i][j][r];
+        if (p.beta != 0.0) v += p.beta * *c;
+        *c = v;
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int BK, bool FAST = false>
 void launch(const Gemm& g, hipStream_t s, int64_t kchunk = 0, int nsplit = 1) {
   Params p;
   p.kchunk = kchunk;
@@ -282,8 +549,13 @@ void launch(const Gemm& g, hipStream_t s, int64_t kchunk = 0, int nsplit = 1) {
   p.transA = g.transA; p.transB = g.transB; p.symA = g.symA; p.uplo = g.uplo;
   p.tiles_m = (int)cdiv(g.m, BM);
   p.tiles_n = (int)cdiv(g.n, BN);
+  const bool kshift_ok = kchunk == 0 || (kchunk % 2 == 0);
+  p.vecA = kshift_ok && ((uintptr_t)g.A % 16 == 0) && (g.lda % 2 == 0) &&
+           (g.batch == 1 || g.strideA % 2 == 0);
+  p.vecB = kshift_ok && ((uintptr_t)g.B % 16 == 0) && (g.ldb % 2 == 0) &&
+           (g.batch == 1 || g.strideB % 2 == 0);
   dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n), (unsigned)(kchunk > 0 ? nsplit : g.batch));
-  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK>), grid, dim3(NT), 0, s, p);
+  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, FAST>), grid, dim3(NT), 0, s, p);
   GEP_LAUNCH_CHECK();
 }
 
@@ -297,6 +569,29 @@ __global__ void splitk_reduce(int64_t m, int64_t n, int nsplit, const double* __
   double v = alpha * acc;
   if (beta != 0.0) v += beta * C[i + j * ldc];
   C[i + j * ldc] = v;
+}
+
+void launch_fast(const Gemm& g, hipStream_t s) {
+  Params p;
+  p.m = g.m; p.n = g.n; p.k = g.k;
+  p.alpha = g.alpha; p.beta = g.beta;
+  p.A = g.A; p.lda = g.lda; p.B = g.B; p.ldb = g.ldb; p.C = g.C; p.ldc = g.ldc;
+  p.sA = p.sB = p.sC = 0;
+  p.transA = g.transA; p.transB = g.transB; p.symA = 0; p.uplo = g.uplo;
+  p.tiles_m = (int)(g.m / 128);
+  p.tiles_n = (int)(g.n / 128);
+  p.kchunk = 0;
+  p.vecA = p.vecB = 1;
+  dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n));
+  if (!g.transA && !g.transB)
+    hipLaunchKernelGGL((dgemm_fast_kernel<false, false>), grid, dim3(NT), 0, s, p);
+  else if (g.transA && !g.transB)
+    hipLaunchKernelGGL((dgemm_fast_kernel<true, false>), grid, dim3(NT), 0, s, p);
+  else if (!g.transA && g.transB)
+    hipLaunchKernelGGL((dgemm_fast_kernel<false, true>), grid, dim3(NT), 0, s, p);
+  else
+    hipLaunchKernelGGL((dgemm_fast_kernel<true, true>), grid, dim3(NT), 0, s, p);
+  GEP_LAUNCH_CHECK();
 }
 
 constexpr int64_t KCHUNK_MIN = 512;
@@ -331,7 +626,7 @@ void gemm(const Gemm& g, hipStream_t s) {
   if (g.work && g.batch == 1 && !g.symA && g.uplo == 0) {
     const int sp = choose_split(g.m, g.n, g.k);
     if (sp > 1 && g.work_elems >= (size_t)sp * g.m * g.n) {
-      const int64_t kc = cdiv(g.k, sp);
+      const int64_t kc = round_up(cdiv(g.k, sp), 16);
       const int nsplit = (int)cdiv(g.k, kc);
       Gemm h = g;
       h.alpha = 1.0; h.beta = 0.0; h.C = g.work; h.ldc = g.m; h.strideC = g.m * g.n;
@@ -345,7 +640,52 @@ void gemm(const Gemm& g, hipStream_t s) {
   }
   const int64_t t128 = cdiv(g.m, 128) * cdiv(g.n, 128) * g.batch;
   if (t128 >= 256 || (g.m > 64 && g.n > 64 && t128 >= 128)) {
-    launch<128, 128, 16>(g, s);
+    // interior tiles on the unchecked kernel, edge strips / k tail on the checked one
+    constexpr int BM = 128, BN = 128, BK = FAST_BK;
+    const int64_t mm = (g.m / BM) * BM, nm = (g.n / BN) * BN, km = (g.k / BK) * BK;
+    const bool aligned = ((uintptr_t)g.A % 16 == 0) && (g.lda % 2 == 0) &&
+                         ((uintptr_t)g.B % 16 == 0) && (g.ldb % 2 == 0);
+    bool ok = aligned && g.batch == 1 && mm > 0 && nm > 0 && km > 0;
+    ok = ok && !g.symA;
+    if (g.uplo == 1) ok = ok && g.m == g.n;
+    if (!ok) {
+      launch<BM, BN, 16>(g, s);
+      return;
+    }
+    Gemm in = g;
+    in.m = mm; in.n = nm; in.k = km;
+    launch_fast(in, s);
+    if (g.k > km) {  // C_interior += alpha op(A)(:, km:) op(B)(km:, :)
+      Gemm t = in;
+      t.k = g.k - km;
+      t.beta = 1.0;
+      t.A = g.transA ? g.A + km : g.A + km * g.lda;
+      t.B = g.transB ? g.B + km * g.ldb : g.B + km;
+      launch<64, 64, 16>(t, s);
+    }
+    if (g.n > nm) {  // right strip: columns nm.., rows 0.. (lower-only: rows nm.. only)
+      Gemm r = g;
+      const int64_t r0 = g.uplo == 1 ? nm : 0;
+      r.m = g.m - r0;
+      r.n = g.n - nm;
+      r.B = g.transB ? g.B + nm : g.B + nm * g.ldb;
+      if (!g.symA) r.A = g.transA ? g.A + r0 * g.lda : g.A + r0;
+      r.C = g.C + r0 + nm * g.ldc;
+      if (g.symA) {
+        r.m = g.m;  // symmetric operand: rows must start at 0 (mm == m, so r0 == 0 here)
+      }
+      launch<64, 64, 16>(r, s);
+    }
+    if (g.m > mm) {  // bottom strip: rows mm.., columns 0..nm (not reached for symmetric A)
+      Gemm bt = g;
+      bt.m = g.m - mm;
+      bt.n = nm;
+      bt.uplo = 0;
+      bt.A = g.transA ? g.A + mm * g.lda : g.A + mm;
+      bt.C = g.C + mm;
+      launch<64, 64, 16>(bt, s);
+    }
+    return;
   } else if (cdiv(g.m, 128) * cdiv(g.n, 64) * g.batch >= 128 && g.m > 64) {
     launch<128, 64, 16>(g, s);
   } else {

@@ -40,10 +40,12 @@ struct BandReduction {
   double* T = nullptr;   // b x b per panel, panel p at T + p*b*b
   double* band = nullptr;
   int64_t ldband = 0;
+  bool coop = true;      // cooperative launch of the panel QR
 };
 size_t sy2sb_workspace(int64_t n, int b);
 void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s);
 // Z (n x ncols) <- Q1 Z with the reflectors left by sy2sb.
+size_t apply_q1_workspace(int64_t n, int64_t ncols, int b);
 void apply_q1(const BandReduction& r, double* Z, int64_t ldz, int64_t ncols, Arena& ws,
               hipStream_t s);
 
@@ -78,6 +80,12 @@ void stedc(int64_t n, const double* d, const double* e, double* lambda, double* 
 // Eigenvalues only, by bisection; bounds2 is 2 doubles of device scratch.
 void stebz_ws(int64_t n, const double* d, const double* e, double* lambda, double* bounds2,
               hipStream_t s);
+
+// ---------------------------------------------------------------- adjoint
+size_t backward_workspace(int64_t M);
+void backward(int64_t M, const double* lam, const double* Y, int64_t ldy, const double* lam_bar,
+              const double* Y_bar, int64_t ldyb, double eta, double tau_c, double* A_bar,
+              int64_t ldab, double* B_bar, int64_t ldbb, Arena& ws, hipStream_t s);
 
 // ---------------------------------------------------------------- finishing
 void sign_fix(int64_t n, int64_t ncols, double* Y, int64_t ldy, hipStream_t s);

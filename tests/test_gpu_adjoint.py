@@ -1,0 +1,134 @@
+"""GPU parity of the adjoint (gep_backward / GEPFunction): against the oracle's
+gradient formula on the oracle's own eigenpairs, and against central finite
+differences of GPU solves on the 4096 workload (decay sqrt(4096/8), seed 5)."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import say, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _gep():
+    import paper_1504_06443_amd as gep
+    return gep
+
+
+@pytest.mark.parametrize("M", [2, 37, 300])
+def test_backward_matches_oracle_formula(gpu, M):
+    say(f"[adjoint] oracle formula M={M}")
+    A, B = synth.banded_pair(M, 4.0, 600 + M)
+    r = oracle.solve(A, B)
+    rng = np.random.default_rng(M)
+    lb = rng.standard_normal(M)
+    Yb = rng.standard_normal((M, M))
+    Ab_o, Bb_o = oracle.gradient(r.lam, r.Y, lb, Yb, eta=1e-3, tau_c=1e-9)
+    Ab, Bb = _gep().backward(to_gpu(r.lam), to_gpu(r.Y), to_gpu(lb), to_gpu(Yb), eta=1e-3,
+                             tau_c=1e-9)
+    Ab, Bb = to_np(Ab), to_np(Bb)
+    assert np.abs(Ab - Ab.T).max() == 0.0 and np.abs(Bb - Bb.T).max() == 0.0
+    assert np.linalg.norm(Ab - Ab_o) <= 1e-12 * np.linalg.norm(Ab_o)
+    assert np.linalg.norm(Bb - Bb_o) <= 1e-12 * np.linalg.norm(Bb_o)
+    # eigenvalue-only cotangent: closed form Y_o Y_o^T / -Y_o Lambda Y_o^T
+    lb2 = np.zeros(M)
+    lb2[: M // 2] = 1.0
+    Ab, Bb = _gep().backward(to_gpu(r.lam), to_gpu(r.Y), to_gpu(lb2), None)
+    Yo = r.Y[:, : M // 2]
+    assert np.abs(to_np(Ab) - Yo @ Yo.T).max() <= 1e-13
+    assert np.abs(to_np(Bb) + Yo @ np.diag(r.lam[: M // 2]) @ Yo.T).max() <= 1e-12
+
+
+def _loss_torch(lam, Y, G, nocc):
+    Yo = Y[:, :nocc]
+    return lam[:nocc].sum() + (G * (Yo @ Yo.T)).sum()
+
+
+def _loss_difference(lp, Yp, lm, Ym, G, nocc):
+    """L(+) - L(-) formed term by term before summing: the loss is ~1e4 while the
+    difference is ~1e-8, so differencing the totals would keep only ~4 digits."""
+    Pp = Yp[:, :nocc] @ Yp[:, :nocc].T
+    Pm = Ym[:, :nocc] @ Ym[:, :nocc].T
+    return ((lp[:nocc] - lm[:nocc]).sum() + (G * (Pp - Pm)).sum()).item()
+
+
+def test_c5_gradient_vs_central_differences(gpu):
+    """L = sum_{k <= M/2} lambda_k + tr(G Y_occ Y_occ^T) at M = 4096: dL/dA, dL/dB
+    against central differences (h = 1e-6) on 20 unit directions (7 A-only, 7 B-only,
+    6 joint)."""
+    import torch
+    gep = _gep()
+    M = 4096
+    say("[adjoint] c5 FD: generating")
+    A, B = synth.workload("m4096_grad")
+    G = synth.symmetric_normal(M, 5001, 1.0 / np.sqrt(M))
+    dA0, dB0, dG = to_gpu(A), to_gpu(B), to_gpu(G)
+    nocc = M // 2
+    Ad = dA0.clone().requires_grad_(True)
+    Bd = dB0.clone().requires_grad_(True)
+    lam, Y = gep.GEPFunction.apply(Ad, Bd)
+    L = _loss_torch(lam, Y, dG, nocc)
+    L.backward()
+    gA, gB = Ad.grad, Bd.grad
+    h = 1e-6
+    # Noise floor of the central difference: the two solves round independently,
+    # about eps * |A|_1 per occupied eigenvalue, adding up like a random walk over
+    # the nocc terms, divided by 2h.  A direction passes if it is within 1e-4
+    # relative or within 10x that floor.
+    eps = np.finfo(np.float64).eps
+    floor = 10.0 * eps * oracle.norm1_sym_lower(A) * np.sqrt(nocc) / (2 * h)
+    worst = 0.0
+    for d in range(20):
+        E = to_gpu(synth.unit_direction(M, 5100 + d))
+        kind = "A" if d < 7 else ("B" if d < 14 else "AB")
+        EA = E if kind in ("A", "AB") else torch.zeros_like(E)
+        EB = E if kind in ("B", "AB") else torch.zeros_like(E)
+        with torch.no_grad():
+            lp, Yp = gep.solve(dA0 + h * EA, dB0 + h * EB)
+            lm, Ym = gep.solve(dA0 - h * EA, dB0 - h * EB)
+            fd = _loss_difference(lp, Yp, lm, Ym, dG, nocc) / (2 * h)
+            an = ((gA * EA).sum() + (gB * EB).sum()).item()
+        err = abs(fd - an)
+        rel = err / max(abs(an), 1e-300)
+        worst = max(worst, min(rel / 1e-4, err / floor))
+        say(f"  dir {d} ({kind}): fd={fd:.10e} an={an:.10e} rel={rel:.2e} abs={err:.2e} "
+            f"floor={floor:.2e}")
+    assert worst <= 1.0, worst
+
+
+def test_gradient_with_degenerate_occupied_eigenvalues(gpu):
+    """An exactly repeated eigenvalue inside the occupied set: the loss is invariant
+    under rotations of that eigenspace, the cut-off tau_c makes the adjoint exact."""
+    import torch
+    gep = _gep()
+    M = 120
+    rng = np.random.default_rng(77)
+    _, B = synth.banded_pair(M, 3.0, 78)
+    LB = np.linalg.cholesky(B)
+    Q, _ = np.linalg.qr(rng.standard_normal((M, M)))
+    mu = np.sort(rng.uniform(-4, 4, M))
+    mu[10:14] = mu[10]
+    A = LB @ Q @ np.diag(mu) @ Q.T @ LB.T
+    A = 0.5 * (A + A.T)
+    G = synth.symmetric_normal(M, 79, 1.0 / np.sqrt(M))
+    dG = to_gpu(G)
+    nocc = M // 2
+    gep.GEPFunction.tau_c = 1e-8
+    try:
+        Ad = to_gpu(A).requires_grad_(True)
+        Bd = to_gpu(B).requires_grad_(True)
+        lam, Y = gep.GEPFunction.apply(Ad, Bd)
+        _loss_torch(lam, Y, dG, nocc).backward()
+    finally:
+        gep.GEPFunction.tau_c = 0.0
+    h = 1e-6
+    for d in range(4):
+        E = to_gpu(synth.unit_direction(M, 900 + d))
+        EA, EB = (E, 0 * E) if d % 2 == 0 else (0 * E, 0.1 * E)
+        with torch.no_grad():
+            lp, Yp = gep.solve(to_gpu(A) + h * EA, to_gpu(B) + h * EB)
+            lm, Ym = gep.solve(to_gpu(A) - h * EA, to_gpu(B) - h * EB)
+            fd = _loss_difference(lp, Yp, lm, Ym, dG, nocc) / (2 * h)
+            an = ((Ad.grad * EA).sum() + (Bd.grad * EB).sum()).item()
+        assert abs(fd - an) <= 1e-5 * max(1.0, abs(an))
