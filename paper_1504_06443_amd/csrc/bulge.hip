@@ -374,15 +374,16 @@ __global__ void __launch_bounds__(NT) q2_form_t(Q2Args a) {
 }
 
 // Z <- (I - V T V^T) Z for every block, groups from last to first, positions in
-// increasing order; one workgroup per strip of SW columns, wave w owning columns
-// [16w, 16w + 16) of the strip through all three products (W1 = V^T Z,
-// W2 = T W1, Z -= V W2), so the products of different waves never meet.  Inside
-// a group the blocks slide down by b rows: the strip's rows live in a circular
-// LDS window, and per block only b rows are written back and b new rows loaded.
-// The V / T / new-row loads of block k+1 are issued into registers before the
-// MFMAs of block k.
-constexpr int SWA = 64;             // columns per workgroup (4 waves x 16)
-constexpr int HB = 128;             // circular window rows (>= HP + b)
+// increasing order; one workgroup per strip of SWA = 32 columns of Z (76 KB of
+// LDS, so two workgroups share a CU).  Inside a group the blocks slide down by b
+// rows: the strip's rows live in a circular LDS window, and per block only b rows
+// are written back and b new rows loaded.  The V / T / new-row loads of block
+// k+1 are issued into registers before the MFMAs of block k.  The three products
+// (W1 = V^T Z, W2 = T W1, Z -= V W2) are computed transposed so every LDS operand
+// read is 16 consecutive doubles; the four waves split each product's 16 x 16
+// tiles.
+constexpr int SWA = 32;             // columns per workgroup
+constexpr int HB = 128;             // circular window rows (>= HP + b - NBW + 1)
 constexpr int ZLD = SWA + 1;
 constexpr int VLD = NBW + 1;
 constexpr int PV = HP * NBW / NT;   // V doubles per thread
@@ -447,19 +448,20 @@ __device__ inline void write_rows(const Q2Args& a, int64_t base, int64_t lo, int
   }
 }
 
-__global__ void __launch_bounds__(NT) q2_apply(Q2Args a) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+q2_apply(Q2Args a) {
   __shared__ double Vs[HP * VLD];        // V[row][c]
   __shared__ double Tt[NBW * VLD];       // T^T[k][j]
   __shared__ double Zs[HB * ZLD];        // Z[slot][col]
-  __shared__ double Wp[4][16 * VLD];     // per wave: W1^T then W2^T [col][c]
+  __shared__ double Ws[SWA * VLD];       // W1^T, then W2^T  [col][c]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int ti = wave >> 1, tj = wave & 1;  // this wave's 16 x 16 tile of W (cols, c)
   const int b = a.b;
   const int64_t c0 = (int64_t)blockIdx.x * SWA;
   const int ncol = (int)((a.ncols - c0) < SWA ? (a.ncols - c0) : SWA);
   const int Hfull = b + NBW - 1;
   const int KS1 = (Hfull + 3) / 4;       // k-steps of W1 (rows beyond Hfull are zero in V)
   for (int idx = tid; idx < HB * ZLD; idx += NT) Zs[idx] = 0.0;
-  double* W = Wp[wave];
   Prefetch f;
   if (a.ngroups > 0) fetch_vt(a, a.ngroups - 1, 0, f);
   for (int64_t j = a.ngroups - 1; j >= 0; --j) {
@@ -498,60 +500,58 @@ __global__ void __launch_bounds__(NT) q2_apply(Q2Args a) {
       } else if (j > 0) {
         fetch_vt(a, j - 1, 0, f);
       }
-      // W1^T (16 x NBW) for this wave's columns: two chains sharing the Z operand
-      v4d w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
-      for (int ks = 0; ks < KS1; ++ks) {
-        const int row = ks * 4 + (lane >> 4);
-        const int slot = (int)((kb + row) & (HB - 1));
-        const double av = Zs[slot * ZLD + wave * 16 + (lane & 15)];
-        const double b0 = Vs[row * VLD + (lane & 15)];
-        const double b1 = Vs[row * VLD + 16 + (lane & 15)];
-        w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, w0, 0, 0, 0);
-        w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, w1, 0, 0, 0);
-      }
+      // W1^T (SWA x NBW) = Z_w^T V, tile (ti, tj)
+      {
+        v4d w = {0.0, 0.0, 0.0, 0.0};
+        for (int ks = 0; ks < KS1; ++ks) {
+          const int row = ks * 4 + (lane >> 4);
+          const int slot = (int)((kb + row) & (HB - 1));
+          const double av = Zs[slot * ZLD + ti * 16 + (lane & 15)];
+          const double bv = Vs[row * VLD + tj * 16 + (lane & 15)];
+          w = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, w, 0, 0, 0);
+        }
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        W[((lane >> 4) + 4 * r) * VLD + (lane & 15)] = w0[r];
-        W[((lane >> 4) + 4 * r) * VLD + 16 + (lane & 15)] = w1[r];
+        for (int r = 0; r < 4; ++r)
+          Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = w[r];
       }
       __syncthreads();
-      // W2^T = W1^T T^T
-      v4d u0 = {0.0, 0.0, 0.0, 0.0}, u1 = {0.0, 0.0, 0.0, 0.0};
+      // W2^T = W1^T T^T, tile (ti, tj)
+      v4d u = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int ks = 0; ks < NBW / 4; ++ks) {
         const int kk = ks * 4 + (lane >> 4);
-        const double av = W[(lane & 15) * VLD + kk];
-        const double b0 = Tt[kk * VLD + (lane & 15)];
-        const double b1 = Tt[kk * VLD + 16 + (lane & 15)];
-        u0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b0, u0, 0, 0, 0);
-        u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, b1, u1, 0, 0, 0);
+        const double av = Ws[(ti * 16 + (lane & 15)) * VLD + kk];
+        const double bv = Tt[kk * VLD + tj * 16 + (lane & 15)];
+        u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
       }
       __syncthreads();
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        W[((lane >> 4) + 4 * r) * VLD + (lane & 15)] = u0[r];
-        W[((lane >> 4) + 4 * r) * VLD + 16 + (lane & 15)] = u1[r];
-      }
+      for (int r = 0; r < 4; ++r)
+        Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = u[r];
       __syncthreads();
-      // Z_w^T -= W2^T V^T : 6 row tiles, independent chains
-      v4d acc[HP / 16];
+      // Z_w^T -= W2^T V^T : (SWA x HP) = 2 x 6 tiles, 3 per wave (column block ti)
+      {
+        v4d acc[3];
 #pragma unroll
-      for (int t = 0; t < HP / 16; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < 3; ++t) acc[t] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < NBW / 4; ++ks) {
-        const int cc = ks * 4 + (lane >> 4);
-        const double av = W[(lane & 15) * VLD + cc];
+        for (int ks = 0; ks < NBW / 4; ++ks) {
+          const int cc = ks * 4 + (lane >> 4);
+          const double av = Ws[(ti * 16 + (lane & 15)) * VLD + cc];
 #pragma unroll
-        for (int t = 0; t < HP / 16; ++t) {
-          const double bv = Vs[(t * 16 + (lane & 15)) * VLD + cc];
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+          for (int t = 0; t < 3; ++t) {
+            const int rt = tj * 3 + t;
+            const double bv = Vs[(rt * 16 + (lane & 15)) * VLD + cc];
+            acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[t], 0, 0, 0);
+          }
         }
-      }
 #pragma unroll
-      for (int t = 0; t < HP / 16; ++t) {
-        const int slot = (int)((kb + t * 16 + (lane & 15)) & (HB - 1));
+        for (int t = 0; t < 3; ++t) {
+          const int rt = tj * 3 + t;
+          const int slot = (int)((kb + rt * 16 + (lane & 15)) & (HB - 1));
 #pragma unroll
-        for (int r = 0; r < 4; ++r) Zs[slot * ZLD + wave * 16 + (lane >> 4) + 4 * r] -= acc[t][r];
+          for (int r = 0; r < 4; ++r) Zs[slot * ZLD + ti * 16 + (lane >> 4) + 4 * r] -= acc[t][r];
+        }
       }
       __syncthreads();
       // rows [kb, kb + b) are final for this group

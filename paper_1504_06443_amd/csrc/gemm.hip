@@ -164,9 +164,18 @@ __global__ void __launch_bounds__(NT) dgemm_kernel(Params p) {
   dgemm_tile<BM, BN, BK, FAST>(p, tm, tn, blockIdx.y);
 }
 
+// 64 x 64 tiles fit two workgroups' registers per SIMD: ask for that occupancy.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+dgemm_kernel_64(Params p) {
+  int tm, tn;
+  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  dgemm_tile<64, 64, 16, false>(p, tm, tn, blockIdx.y);
+}
+
 // Problems whose sizes live in device memory (written by an earlier kernel).
 template <int BM, int BN, int BK>
-__global__ void __launch_bounds__(NT) dgemm_grouped_kernel(const GemmDesc* __restrict__ desc) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+dgemm_grouped_kernel(const GemmDesc* __restrict__ desc) {
   const GemmDesc d = desc[blockIdx.y];
   if (d.m <= 0 || d.n <= 0) return;
   const int tiles_m = (int)((d.m + BM - 1) / BM), tiles_n = (int)((d.n + BN - 1) / BN);
@@ -555,7 +564,10 @@ void launch(const Gemm& g, hipStream_t s, int64_t kchunk = 0, int nsplit = 1) {
   p.vecB = kshift_ok && ((uintptr_t)g.B % 16 == 0) && (g.ldb % 2 == 0) &&
            (g.batch == 1 || g.strideB % 2 == 0);
   dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n), (unsigned)(kchunk > 0 ? nsplit : g.batch));
-  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, FAST>), grid, dim3(NT), 0, s, p);
+  if (BM == 64 && BN == 64 && BK == 16 && !FAST)
+    hipLaunchKernelGGL(dgemm_kernel_64, grid, dim3(NT), 0, s, p);
+  else
+    hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, FAST>), grid, dim3(NT), 0, s, p);
   GEP_LAUNCH_CHECK();
 }
 
@@ -686,8 +698,6 @@ void gemm(const Gemm& g, hipStream_t s) {
       launch<64, 64, 16>(bt, s);
     }
     return;
-  } else if (cdiv(g.m, 128) * cdiv(g.n, 64) * g.batch >= 128 && g.m > 64) {
-    launch<128, 64, 16>(g, s);
   } else {
     launch<64, 64, 16>(g, s);
   }
