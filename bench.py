@@ -63,6 +63,29 @@ def cpu_baseline(M_target: int, sample: int) -> dict:
                       f"(M/{sample})^3 to M={M_target}"}
 
 
+def kernel_traffic(kernel: str, workload: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/<kernel>_<workload>_traffic.txt (FETCH_SIZE + WRITE_SIZE, calibrated
+    against a plain copy), or None when there is none or the kernel's source file
+    has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            fields[k.strip()] = v.strip()
+    src = fields.get("source")
+    if not src or "bytes_per_launch" not in fields:
+        return None
+    digest = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+    if digest != fields.get("source_sha256"):
+        return None
+    return float(fields["bytes_per_launch"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +95,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=1536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -98,6 +122,7 @@ def main() -> int:
     torch.cuda.synchronize()
 
     gep.profile_enable(True)
+    gep.probe_enable(False)
     for i in range(args.warmup):
         lam, Y = gep.solve(dA, dB)
         torch.cuda.synchronize()
@@ -105,6 +130,8 @@ def main() -> int:
         del lam, Y
     times = []
     phases = {}
+    gep.probe_read()  # drop anything recorded before the timed region
+    gep.probe_enable(True)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for i in range(args.steps):
@@ -118,39 +145,76 @@ def main() -> int:
         print(f"[bench] step {i}: {times[-1]:.3f}s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    gep.probe_enable(False)
+    probes = gep.probe_read()
     ms_per_step = 1000.0 * elapsed / args.steps
     solves_per_s = args.steps / elapsed
     F = alg_flops(M)
     tflops = F / (elapsed / args.steps) / 1e12
     phase_ms = {k: float(np.median(v)) for k, v in phases.items()}
 
-    # dominant phase and its roofline (MFMA-bound phases against the FP64 peak)
     b = band_width(M)
-    dom = max((k for k in phase_ms if k in PHASE_FLOPS), key=lambda k: phase_ms[k])
-    dom_tf = PHASE_FLOPS[dom](M, b) / (phase_ms[dom] / 1e3) / 1e12
-    bound = "alu" if dom == "S2" else "mfma"
-    roofline = {"bound": bound, "achieved": dom_tf, "peak": PEAK_FP64, "unit": "TFLOP/s",
-                "frac": dom_tf / PEAK_FP64, "traffic": None, "phase": dom,
-                "phase_ms": phase_ms[dom]}
+    workload = f"m{M}"
+    # Dominant kernel: the probed kernel with the most time in the timed steps;
+    # achieved = its algorithmic flops per launch / its mean launch time (HIP
+    # events on the stream it is launched on).  The chase is latency bound and
+    # priced against the FP64 vector ALU peak; the rest are matrix-core kernels.
+    dom = max(probes, key=lambda k: probes[k][1])
+    n_launch, dom_ms, dom_flops = probes[dom]
+    avg_ms = dom_ms / max(n_launch, 1)
+    achieved = (dom_flops / max(n_launch, 1)) / (avg_ms / 1e3) / 1e12 if n_launch else 0.0
+    bound = "alu" if dom in ("chase_kernel", "panel_qr_coop") else "mfma"
+    roofline = {"bound": bound, "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64, "traffic": kernel_traffic(dom, workload),
+                "kernel": dom, "launches_per_step": n_launch / args.steps,
+                "avg_launch_ms": avg_ms,
+                "share_of_step": dom_ms / (elapsed * 1e3),
+                "all_kernels": {k: {"launches_per_step": v[0] / args.steps,
+                                    "ms_per_step": v[1] / args.steps,
+                                    "tflops": (v[2] / (v[1] / 1e3) / 1e12) if v[1] > 0 else None}
+                                for k, v in probes.items()}}
 
-    check = None
-    if not args.no_check:
-        info = gep.api._info(dev)
-        # invariants at full size, on the GPU with torch matmuls (independent of libgep)
+    def invariants(lam_, Y_):
+        """Residual ||A Y - B Y Lambda||_1 / (||A||_1 ||Y||_1) and max |Y^T B Y - I| at
+        full size, on the GPU with torch matmuls (independent of libgep)."""
         with torch.no_grad():
-            Asym = torch.triu(dA) + torch.triu(dA, 1).t()
-            Bsym = torch.triu(dB) + torch.triu(dB, 1).t()
-            Yc = Y.contiguous()
-            AY = Asym @ Yc
-            BY = Bsym @ Yc
-            n1 = Asym.abs().sum(0).max().item()
-            res = ((AY - BY * lam[None, :]).abs().sum(0).max() / (n1 * Yc.abs().sum(0).max())).item()
+            Yc = Y_.contiguous()
+            AY = dA @ Yc
+            BY = dB @ Yc
+            n1 = dA.abs().sum(0).max().item()
+            res = ((AY - BY * lam_[None, :]).abs().sum(0).max() / (n1 * Yc.abs().sum(0).max())).item()
             del AY
             G = Yc.t() @ BY
             G.diagonal().sub_(1.0)
             orth = G.abs().max().item()
-            del G, BY
-        check = {"residual": res, "orth": orth, "norm1_A": n1}
+            del G, BY, Yc
+        torch.cuda.empty_cache()
+        return {"residual": res, "orth": orth, "norm1_A": n1}
+
+    check = None if args.no_check else {"fp64": invariants(lam, Y)}
+
+    # Mixed precision (FP32-arithmetic trailing updates + FP64 refinement): one
+    # solve after the timed FP64 steps, its eigenvalues against the FP64 path's.
+    mixed = None
+    if not args.no_mixed:
+        lam64 = lam.clone()
+        del Y
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        tm = time.perf_counter()
+        lam_m, Y = gep.solve(dA, dB, prec="mixed", check_info=False)
+        torch.cuda.synchronize()
+        t_mixed = time.perf_counter() - tm
+        ph_m = gep.profile_read()
+        n1 = dA.abs().sum(0).max().item()
+        err = ((lam_m - lam64).abs().max() / n1).item()
+        mixed = {"seconds": t_mixed, "err_vs_fp64": err,
+                 "speedup": (elapsed / args.steps) / t_mixed if err <= 1e-11 else None,
+                 "phase_ms": ph_m}
+        print(f"[bench] mixed solve {t_mixed:.3f}s, |dlambda|/|A|_1 vs FP64 {err:.2e}",
+              file=sys.stderr, flush=True)
+        if check is not None:
+            check["mixed"] = invariants(lam_m, Y)
 
     out = {
         "metric": METRIC,
@@ -170,7 +234,8 @@ def main() -> int:
         "tflops_fp64": tflops,
         "alg_flops_per_solve": F,
         "phase_ms": phase_ms,
-        "mixed_speedup": None,
+        "mixed_speedup": mixed["speedup"] if mixed else None,
+        "mixed": mixed,
         "roofline": roofline,
         "check": check,
     }

@@ -76,7 +76,15 @@ size_t gep_workspace_size(int64_t M, int job, int prec);
  *   A [lda x M], B [ldb x M]: lower triangles read.
  *   lambda [M]: eigenvalues, ascending.
  *   Y [ldy x M]: B-orthonormal eigenvectors (unused and may be NULL for VALUES).
- *   prec: GEP_PREC_FP64 (every step in FP64).
+ *   prec: GEP_PREC_FP64 (every step in FP64), or GEP_PREC_MIXED (job must be
+ *     GEP_JOB_VECTORS): the interior GEMM tiles of the Cholesky, the reduced
+ *     matrix, the full -> band reduction, the Q1 back-transformation and
+ *     Y = L^-T Z run in FP32 arithmetic (FP64 storage; Cholesky diagonal blocks,
+ *     bulge chase, Q2 and the tridiagonal solver stay FP64), then one FP64
+ *     refinement pass: S = Y^T A Y and T = Y^T B Y in FP64, exact FP64 solves of
+ *     gap-aligned blocks of consecutive eigenvalues, and first-order coupling
+ *     between blocks (eigenvalues corrected to second order).  This extends the
+ *     paper, which uses FP64 throughout.
  *   workspace: >= gep_workspace_size(M, job, prec) bytes, 256-byte aligned.
  *   info: device int32, see above.
  */
@@ -169,10 +177,14 @@ int gep_backward(int64_t M, const double* lambda, const double* Y, int64_t ldy,
  * (the contraction every blocked step of the solver is made of).  op(X) = X or
  * X^T (trans = 0 / 1); op(A) is m x k, op(B) k x n, C m x n, all column-major
  * device pointers.  uplo = 1 writes only the lower triangle of C (m == n).
+ * arith = 0: FP64 arithmetic throughout.  arith = 1: the 128 x 128 interior tiles
+ * round both operands to FP32 and accumulate in FP32 on the matrix cores (the
+ * mixed-precision solver's trailing updates); inputs and outputs stay FP64,
+ * edge strips stay FP64.  Any other value returns GEP_ERR_ARG (argument 15).
  */
 int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k, double alpha,
               const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-              int64_t ldc, void* stream);
+              int64_t ldc, int arith, void* stream);
 
 /*
  * Per-phase timing of the last gep_solve on this process: when enabled,
@@ -180,10 +192,28 @@ int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k,
  * gep_profile_read synchronises on the last event and writes up to n phase times
  * in milliseconds, in the order R1 (Cholesky), R2-4 (reduced matrix), S1 (full ->
  * band), S2 (band -> tridiagonal), S3 (tridiagonal eigensolver), S4 (Q2), S5 (Q1),
- * R5 (Y = L^{-T} Z), F (sort / sign).  Returns the number of phases written.
+ * R5 (Y = L^{-T} Z), REF (mixed-precision refinement; zero for FP64), F (sign
+ * convention).  Returns the number of phases written.
  */
 int gep_profile_enable(int on);
 int gep_profile_read(double* ms, int n);
+
+/*
+ * Launch probes: when enabled, every launch of the probed kernels records a HIP
+ * event pair on the stream it is launched on, with the launch's algorithmic
+ * flops.  Kernels: 0 = the 128 x 128 interior GEMM tile kernel (flops 2 m n k,
+ * or k n (n + 1) for a lower-triangle product), 1 = the Q2 application (2 n^2
+ * ncols), 2 = the bulge chase (6 b n^2), 3 = the band-reduction panel QR
+ * (2 n w^2 - 2 w^3 / 3 for an n x w panel).
+ * gep_probe_read synchronises on the recorded events, returns the number of
+ * launches, their summed duration in milliseconds and their summed flops since
+ * the previous read of that kernel, and forgets them.  Any output pointer may be
+ * NULL.  An unknown kernel index returns GEP_ERR_ARG (argument 1).
+ * gep_probe_name returns the kernel's name (NULL for an unknown index).
+ */
+int gep_probe_enable(int on);
+int gep_probe_read(int kernel, int64_t* launches, double* ms, double* flops);
+const char* gep_probe_name(int kernel);
 
 #ifdef __cplusplus
 }

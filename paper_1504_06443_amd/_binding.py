@@ -59,9 +59,12 @@ SIGNATURES = {
     "gep_tridiag_eig": (INT, [I64, P, P, P, P, I64, INT, P, SZ, P, P]),
     "gep_backward_workspace_size": (SZ, [I64]),
     "gep_backward": (INT, [I64, P, P, I64, P, P, I64, DBL, DBL, P, I64, P, I64, P, SZ, P]),
-    "gep_dgemm": (INT, [INT, INT, INT, I64, I64, I64, DBL, P, I64, P, I64, DBL, P, I64, P]),
+    "gep_dgemm": (INT, [INT, INT, INT, I64, I64, I64, DBL, P, I64, P, I64, DBL, P, I64, INT, P]),
     "gep_profile_enable": (INT, [INT]),
     "gep_profile_read": (INT, [P, INT]),
+    "gep_probe_enable": (INT, [INT]),
+    "gep_probe_read": (INT, [INT, P, P, P]),
+    "gep_probe_name": (ctypes.c_char_p, [INT]),
 }
 
 

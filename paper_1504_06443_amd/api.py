@@ -7,7 +7,7 @@ import torch
 
 from ._binding import JOB_VALUES, JOB_VECTORS, PREC_FP64, PREC_MIXED, check, lib
 
-PHASES = ("R1", "R2-4", "S1", "S2", "S3", "S4", "S5", "R5", "F")
+PHASES = ("R1", "R2-4", "S1", "S2", "S3", "S4", "S5", "R5", "REF", "F")
 
 _JOBS = {"values": JOB_VALUES, "vectors": JOB_VECTORS, JOB_VALUES: JOB_VALUES,
          JOB_VECTORS: JOB_VECTORS}
@@ -138,9 +138,10 @@ def tridiag_eig(d: torch.Tensor, e: torch.Tensor, job="vectors", check_info=True
 
 
 def dgemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, alpha=1.0, beta=0.0,
-          lower_only=False):
-    """C = alpha A B + beta C on libgep's FP64 MFMA GEMM (row-major torch views are
-    handled as transposed column-major operands)."""
+          lower_only=False, fp32_arith=False):
+    """C = alpha A B + beta C on libgep's MFMA GEMM (row-major torch views are
+    handled as transposed column-major operands).  fp32_arith: interior tiles in
+    FP32 arithmetic (FP64 storage)."""
     m, k = A.shape
     k2, n = B.shape
     assert k == k2
@@ -151,7 +152,8 @@ def dgemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor | None = None, alpha
     assert C.is_contiguous()
     # row-major C = A B  <=>  column-major C^T = B^T A^T
     st = lib().gep_dgemm(0, 0, 1 if lower_only else 0, n, m, k, float(alpha), _ptr(B), max(n, 1),
-                         _ptr(A), max(k, 1), float(beta), _ptr(C), max(n, 1), _stream())
+                         _ptr(A), max(k, 1), float(beta), _ptr(C), max(n, 1),
+                         1 if fp32_arith else 0, _stream())
     check(st, "gep_dgemm")
     return C
 
@@ -164,6 +166,28 @@ def profile_read() -> dict:
     buf = (ctypes.c_double * len(PHASES))()
     n = lib().gep_profile_read(ctypes.cast(buf, ctypes.c_void_p), len(PHASES))
     return {PHASES[i]: buf[i] for i in range(n)}
+
+
+PROBE_KERNELS = ("dgemm_fast_kernel", "q2_apply", "chase_kernel", "panel_qr_coop")
+
+
+def probe_enable(on: bool = True) -> None:
+    """Record HIP events around every launch of the probed kernels (see gep.h)."""
+    check(lib().gep_probe_enable(1 if on else 0), "gep_probe_enable")
+
+
+def probe_read() -> dict:
+    """{kernel name: (launches, summed ms, summed algorithmic flops)} since the last
+    read; synchronises on the recorded events."""
+    out = {}
+    for i, name in enumerate(PROBE_KERNELS):
+        n = ctypes.c_int64(0)
+        ms = ctypes.c_double(0.0)
+        fl = ctypes.c_double(0.0)
+        check(lib().gep_probe_read(i, ctypes.byref(n), ctypes.byref(ms), ctypes.byref(fl)),
+              "gep_probe_read")
+        out[name] = (int(n.value), float(ms.value), float(fl.value))
+    return out
 
 
 class BatchedSolver:

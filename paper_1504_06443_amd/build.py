@@ -12,7 +12,8 @@ OBJ = os.path.join(HERE, "_obj")
 LIB = os.path.join(HERE, "libgep.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["abi.hip", "gemm.hip", "misc.hip", "chol.hip", "band.hip", "bulge.hip", "dc.hip", "adjoint.hip"]
+SOURCES = ["abi.hip", "gemm.hip", "misc.hip", "chol.hip", "band.hip", "bulge.hip", "dc.hip", "adjoint.hip",
+           "runtime.hip", "refine.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed-FP32 instructions stay off: they have produced silent wrong results
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -63,7 +63,7 @@ __global__ void band_copy_out(int64_t n, int b, const double* __restrict__ band,
 }
 
 // ---------------------------------------------------------------- profiling
-constexpr int NPHASE = 9;
+constexpr int NPHASE = 10;
 bool g_prof = false;
 hipEvent_t g_ev[NPHASE + 1];
 bool g_ev_ok = false;
@@ -88,7 +88,10 @@ struct Plan {
   int64_t M;
   int b;
   int64_t ldband, kmax, nblk;
-  bool vectors;
+  bool vectors, mixed;
+  char* refine_ws;  // mixed precision: refinement workspace
+  size_t refine_bytes;
+  double* coupling;
   double *L, *Linv, *tmp, *C, *T1, *band, *d, *e, *V2, *tau2, *bounds;
   int32_t *sync, *err;
   char* scratch;  // phase scratch (reused by S1, S3, S4, S5)
@@ -107,10 +110,11 @@ size_t phase_scratch_bytes(int64_t M, int b, bool vectors) {
   return s;
 }
 
-void carve(Plan& p, Arena& a, int64_t M, bool vectors) {
+void carve(Plan& p, Arena& a, int64_t M, bool vectors, bool mixed = false) {
   p.M = M;
   p.b = default_band(M);
   p.vectors = vectors;
+  p.mixed = mixed;
   p.ldband = 2 * p.b + 1;
   p.kmax = M > 1 ? cdiv(M - 1, p.b) : 1;
   p.nblk = cdiv(M, NB);
@@ -133,6 +137,14 @@ void carve(Plan& p, Arena& a, int64_t M, bool vectors) {
   }
   p.scratch_bytes = phase_scratch_bytes(M, p.b, vectors);
   p.scratch = a.take<char>(p.scratch_bytes);
+  p.refine_ws = nullptr;
+  p.refine_bytes = 0;
+  p.coupling = nullptr;
+  if (mixed) {
+    p.refine_bytes = refine_workspace(M);
+    p.refine_ws = a.take<char>(p.refine_bytes);
+    p.coupling = a.take<double>(1);
+  }
 }
 
 Arena scratch_arena(const Plan& p) {
@@ -184,19 +196,25 @@ int guarded(F&& f) {
 
 // One generalized eigenproblem, enqueued on s (arguments already validated).
 // coop: launch the panel QR cooperatively (co-residency guaranteed by the runtime);
-// prof: record the phase events.
+// prof: record the phase events.  mixed (vectors only): the interior GEMM tiles of
+// R1, R2-4, S1, S5 and R5 run in FP32 arithmetic, S2-S4 and the diagonal blocks of
+// the Cholesky stay FP64, and the eigenpairs are then refined in FP64 (REF).
 void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
                double* lambda, double* Y, int64_t ldy, bool vectors, void* workspace,
-               size_t ws_bytes, int32_t* info, hipStream_t s, bool coop, bool prof_on) {
+               size_t ws_bytes, int32_t* info, hipStream_t s, bool coop, bool prof_on,
+               bool mixed = false) {
   fill_i32(info, 1, 0, s);
   if (M == 0) return;
+  mixed = mixed && vectors;
   Plan p;
   Arena a;
   a.base = (char*)workspace;
   a.cap = ws_bytes;
-  carve(p, a, M, vectors);
+  carve(p, a, M, vectors, mixed);
   Prof prof(s);
   Prof* pp = prof_on ? &prof : nullptr;
+  const MathMode trailing = mixed ? MathMode::Fp32 : MathMode::Fp64;
+  MathScope scope(trailing);
   if (pp) pp->mark(0);
   reduce_steps(p, A, lda, B, ldb, info, s, pp);
   {
@@ -211,10 +229,11 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
   if (!vectors) {
     stebz_ws(M, p.d, p.e, lambda, p.bounds, s);
     if (pp)
-      for (int i = 5; i <= 9; ++i) pp->mark(i);
+      for (int i = 5; i <= NPHASE; ++i) pp->mark(i);
     return;
   }
   {
+    MathScope fp64(MathMode::Fp64);
     Arena sa = scratch_arena(p);
     stedc(M, p.d, p.e, lambda, Y, ldy, info, sa, s);
   }
@@ -231,9 +250,17 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
   if (pp) pp->mark(7);
   trsm_llt(Tri{p.L, M, p.Linv, 0}, M, Y, ldy, M, p.tmp, s);
   if (pp) pp->mark(8);
+  if (mixed) {
+    // L and C are no longer needed: they are the refinement's M x M scratch
+    Arena ra;
+    ra.base = p.refine_ws;
+    ra.cap = p.refine_bytes;
+    refine(M, A, lda, B, ldb, Y, ldy, lambda, p.L, p.C, ra, p.coupling, s);
+  }
+  if (pp) pp->mark(9);
   hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
   GEP_LAUNCH_CHECK();
-  if (pp) pp->mark(9);
+  if (pp) pp->mark(10);
 }
 
 // ---------------------------------------------------------------- batches
@@ -339,15 +366,14 @@ const char* gep_status_string(int status) {
 
 int gep_last_bad_arg(void) { return g_bad_arg; }
 
-const char* gep_version(void) { return "libgep 0.1 (gfx950, FP64)"; }
+const char* gep_version(void) { return "libgep 0.2 (gfx950; FP64 and FP32/FP64 mixed)"; }
 
 size_t gep_workspace_size(int64_t M, int job, int prec) {
-  (void)prec;
   if (M <= 0) return 256;
   Plan p;
   Arena a;
   a.dry = true;
-  carve(p, a, M, job == GEP_JOB_VECTORS);
+  carve(p, a, M, job == GEP_JOB_VECTORS, prec == GEP_PREC_MIXED && job == GEP_JOB_VECTORS);
   return a.used + 256;
 }
 
@@ -367,7 +393,7 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
     if (M > 0 && !Y) return bad(7);
     if (ldy < m1) return bad(8);
   }
-  if (prec != GEP_PREC_FP64) return bad(10);
+  if (prec != GEP_PREC_FP64 && !(prec == GEP_PREC_MIXED && job == GEP_JOB_VECTORS)) return bad(10);
   if (!info) return bad(13);
   const size_t need = gep_workspace_size(M, job, prec);
   if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(11);
@@ -375,7 +401,7 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
   hipStream_t s = (hipStream_t)stream;
   return guarded([&]() -> int {
     solve_one(M, A, lda, B, ldb, lambda, Y, ldy, job == GEP_JOB_VECTORS, workspace, ws_bytes, info,
-              s, true, true);
+              s, true, true, prec == GEP_PREC_MIXED);
     return GEP_OK;
   });
 }
@@ -671,7 +697,7 @@ int gep_backward(int64_t M, const double* lambda, const double* Y, int64_t ldy,
 
 int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k, double alpha,
               const double* A, int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-              int64_t ldc, void* stream) {
+              int64_t ldc, int arith, void* stream) {
   g_bad_arg = 0;
   if (transA != 0 && transA != 1) return bad(1);
   if (transB != 0 && transB != 1) return bad(2);
@@ -686,7 +712,9 @@ int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k,
   if (ldb < (brows > 1 ? brows : 1)) return bad(11);
   if (m > 0 && n > 0 && !C) return bad(13);
   if (ldc < (m > 1 ? m : 1)) return bad(14);
+  if (arith != 0 && arith != 1) return bad(15);
   return guarded([&]() -> int {
+    MathScope mode(arith == 1 ? MathMode::Fp32 : MathMode::Fp64);
     Gemm g;
     g.transA = transA; g.transB = transB; g.uplo = uplo;
     g.m = m; g.n = n; g.k = k; g.alpha = alpha; g.beta = beta;
@@ -699,6 +727,29 @@ int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k,
 int gep_profile_enable(int on) {
   g_prof = on != 0;
   return GEP_OK;
+}
+
+int gep_probe_enable(int on) {
+  probe_enable(on != 0);
+  return GEP_OK;
+}
+
+int gep_probe_read(int kernel, int64_t* launches, double* ms, double* flops) {
+  if (kernel < 0 || kernel >= PROBE_COUNT) return bad(1);
+  return guarded([&]() -> int {
+    probe_read(kernel, launches, ms, flops);
+    return GEP_OK;
+  });
+}
+
+const char* gep_probe_name(int kernel) {
+  switch (kernel) {
+    case PROBE_GEMM: return "dgemm_fast_kernel";
+    case PROBE_Q2_APPLY: return "q2_apply";
+    case PROBE_CHASE: return "chase_kernel";
+    case PROBE_PANEL_QR: return "panel_qr_coop";
+    default: return nullptr;
+  }
 }
 
 int gep_profile_read(double* ms, int n) {

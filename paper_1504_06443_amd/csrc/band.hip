@@ -318,6 +318,9 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
       pa.col0 = col0; pa.b = b; pa.rows_per = (int)cdiv(n, G); pa.err = err;
       pa.timeout_ticks = timeout_ticks;
       if (pa.rows_per > 256) throw HipError{hipErrorInvalidValue, "panel too tall"};
+      // Householder QR of an n x kmax panel: 2 n kmax^2 - 2 kmax^3 / 3 flops
+      ProbeScope probe(PROBE_PANEL_QR, s,
+                       2.0 * (double)n * kmax * kmax - 2.0 * (double)kmax * kmax * kmax / 3.0);
       if (r.coop) {
         void* args[] = {&pa};
         GEP_HIP(hipLaunchCooperativeKernel((const void*)panel_qr_coop, dim3(G), dim3(NT), args,

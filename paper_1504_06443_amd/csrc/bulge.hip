@@ -588,8 +588,12 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
   a.T = ws.take<double>((size_t)a.ngroups * a.kmax * NBW * NBW);
   hipLaunchKernelGGL(q2_form_t, dim3((unsigned)a.kmax, (unsigned)a.ngroups), dim3(NT), 0, s, a);
   GEP_LAUNCH_CHECK();
-  hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
-  GEP_LAUNCH_CHECK();
+  {
+    // algorithmic flops: ~n^2 / (2b) reflectors of length b, 4b flops per column each
+    ProbeScope probe(PROBE_Q2_APPLY, s, 2.0 * (double)n * (double)n * (double)ncols);
+    hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
+    GEP_LAUNCH_CHECK();
+  }
 }
 
 size_t sb2st_reflector_count(int64_t n, int b) {
@@ -623,6 +627,7 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     if (rate_khz <= 0) rate_khz = 100000;
     a.timeout_ticks = (uint64_t)rate_khz * 1000ull * 10ull;  // 10 s for any single wait
     int64_t groups = nsweeps < 512 ? nsweeps : 512;
+    ProbeScope probe(PROBE_CHASE, s, 6.0 * c.b * (double)n * (double)n);
     hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(NT), 0, s, a);
     GEP_LAUNCH_CHECK();
   }

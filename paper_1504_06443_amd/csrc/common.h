@@ -91,20 +91,38 @@ struct GemmDesc {
 void gemm_grouped(const GemmDesc* desc, int count, int64_t max_m, int64_t max_n, hipStream_t s);
 size_t splitk_work_elems(int64_t m, int64_t n, int64_t k);
 
-// Same contraction in FP32 storage and FP32 MFMA accumulation.
-struct GemmF {
-  bool transA = false, transB = false;
-  int uplo = 0;
-  int64_t m = 0, n = 0, k = 0;
-  float alpha = 1.0f, beta = 0.0f;
-  const float* A = nullptr;
-  int64_t lda = 0;
-  const float* B = nullptr;
-  int64_t ldb = 0;
-  float* C = nullptr;
-  int64_t ldc = 0;
+// Arithmetic of the 128 x 128 interior GEMM tiles.  FP64 by default; under
+// MathMode::Fp32 both operands are rounded to FP32 as they are staged in LDS and
+// the products accumulate in FP32 on the matrix cores, while inputs and outputs
+// stay FP64 in memory.  Edge strips and small problems always run in FP64.  The
+// mode belongs to the calling host thread and is set by a MathScope.
+enum class MathMode { Fp64 = 0, Fp32 = 1 };
+MathMode math_mode();
+struct MathScope {
+  MathMode saved;
+  explicit MathScope(MathMode m);
+  ~MathScope();
+  MathScope(const MathScope&) = delete;
+  MathScope& operator=(const MathScope&) = delete;
 };
-void gemm_f32(const GemmF& g, hipStream_t s);
+
+// Launch timing: when enabled, a ProbeScope records a HIP event pair on the
+// launch stream around one kernel launch and remembers the launch's algorithmic
+// flops.  Off by default (no events are recorded then).
+enum ProbeKernel { PROBE_GEMM = 0, PROBE_Q2_APPLY = 1, PROBE_CHASE = 2, PROBE_PANEL_QR = 3,
+                   PROBE_COUNT = 4 };
+void probe_enable(bool on);
+bool probe_read(int id, int64_t* launches, double* ms, double* flops);
+struct ProbeScope {
+  int id;
+  hipStream_t s;
+  double flops;
+  bool on;
+  ProbeScope(int id_, hipStream_t s_, double flops_);
+  ~ProbeScope();
+  ProbeScope(const ProbeScope&) = delete;
+  ProbeScope& operator=(const ProbeScope&) = delete;
+};
 
 // Small elementwise helpers (in misc.hip).
 void copy_matrix(int64_t m, int64_t n, const double* src, int64_t lds, double* dst, int64_t ldd,

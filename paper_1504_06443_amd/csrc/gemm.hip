@@ -16,6 +16,8 @@
 //    equal mod 8) take a contiguous range of tiles, and that range is walked in
 //    groups of 8 tile rows, which keeps the shared A rows / B columns in that
 //    XCD's L2.
+#include <type_traits>
+
 #include "common.h"
 
 namespace gep {
@@ -411,19 +413,39 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
 
 constexpr int FAST_BK = 16;
 
+// two consecutive staged elements in one LDS write (even offsets)
+__device__ inline void store_pair(double* dst, double2 v) { *reinterpret_cast<double2*>(dst) = v; }
+__device__ inline void store_pair(float* dst, double2 v) {
+  *reinterpret_cast<float2*>(dst) = make_float2((float)v.x, (float)v.y);
+}
+
+__device__ inline v4d mfma16(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline v4f mfma16(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 // Interior region: 128 x 128 tiles, BK = FAST_BK, k a multiple of BK, operands 16-byte
 // aligned with even leading dimensions, transposes fixed at compile time.  The
 // steady-state loop has no control flow besides the loop itself, which keeps the
 // accumulators resident in the matrix-core registers.
-template <bool TA, bool TB>
+//
+// F32: the staged operands are rounded to FP32 and multiplied with
+// v_mfma_f32_16x16x4f32 (FP32 accumulation, twice the FP64 rate).  Its output
+// layout differs from the FP64 instruction's: register r of lane l holds row
+// 4 (l / 16) + r of the 16 x 16 block instead of l / 16 + 4 r.
+template <bool TA, bool TB, bool F32>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 dgemm_fast_kernel(Params p) {
+  using S = typename std::conditional<F32, float, double>::type;
+  using Acc = typename std::conditional<F32, v4f, v4d>::type;
   constexpr int BM = 128, BN = 128, BK = FAST_BK, PAD = 4;
   constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
   constexpr int WM = 64, WN = 64, FR = 4, FC = 4;
   constexpr int PA2 = BM * BK / 2 / NT, PB2 = BN * BK / 2 / NT;
-  __shared__ double As[2][BK * LDA_S];
-  __shared__ double Bs[2][BK * LDB_S];
+  __shared__ S As[2][BK * LDA_S];
+  __shared__ S Bs[2][BK * LDB_S];
   int tm, tn;
   tile_coords(p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
@@ -476,43 +498,43 @@ dgemm_fast_kernel(Params p) {
   {                                                                                       \
     _Pragma("unroll") for (int i = 0; i < PA2; ++i) {                                     \
       if (!TA) {                                                                          \
-        *reinterpret_cast<double2*>(&As[buf_][as_off[i]]) = ra[i];                        \
+        store_pair(&As[buf_][as_off[i]], ra[i]);                                          \
       } else {                                                                            \
-        As[buf_][as_off[i]] = ra[i].x;                                                    \
-        As[buf_][as_off[i] + LDA_S] = ra[i].y;                                            \
+        As[buf_][as_off[i]] = (S)ra[i].x;                                                 \
+        As[buf_][as_off[i] + LDA_S] = (S)ra[i].y;                                         \
       }                                                                                   \
     }                                                                                     \
     _Pragma("unroll") for (int i = 0; i < PB2; ++i) {                                     \
       if (!TB) {                                                                          \
-        Bs[buf_][bs_off[i]] = rb[i].x;                                                    \
-        Bs[buf_][bs_off[i] + LDB_S] = rb[i].y;                                            \
+        Bs[buf_][bs_off[i]] = (S)rb[i].x;                                                 \
+        Bs[buf_][bs_off[i] + LDB_S] = (S)rb[i].y;                                         \
       } else {                                                                            \
-        *reinterpret_cast<double2*>(&Bs[buf_][bs_off[i]]) = rb[i];                        \
+        store_pair(&Bs[buf_][bs_off[i]], rb[i]);                                          \
       }                                                                                   \
     }                                                                                     \
   }
 #define GEP_FAST_COMPUTE(buf_)                                                            \
   {                                                                                       \
-    const double* as = As[buf_];                                                          \
-    const double* bs = Bs[buf_];                                                          \
+    const S* as = As[buf_];                                                               \
+    const S* bs = Bs[buf_];                                                               \
     _Pragma("unroll") for (int ks = 0; ks < BK / 4; ++ks) {                               \
       const int krow = ks * 4 + (lane >> 4);                                              \
-      double af[FR], bf[FC];                                                              \
+      S af[FR], bf[FC];                                                                   \
       _Pragma("unroll") for (int i = 0; i < FR; ++i) af[i] =                              \
           as[krow * LDA_S + wr * WM + i * 16 + (lane & 15)];                              \
       _Pragma("unroll") for (int j = 0; j < FC; ++j) bf[j] =                              \
           bs[krow * LDB_S + wc * WN + j * 16 + (lane & 15)];                              \
       _Pragma("unroll") for (int i = 0; i < FR; ++i)                                      \
           _Pragma("unroll") for (int j = 0; j < FC; ++j) acc[i][j] =                      \
-              __builtin_amdgcn_mfma_f64_16x16x4f64(bf[j], af[i], acc[i][j], 0, 0, 0);     \
+              mfma16(bf[j], af[i], acc[i][j]);                                            \
     }                                                                                     \
   }
 
-  v4d acc[FR][FC];
+  Acc acc[FR][FC];
 #pragma unroll
   for (int i = 0; i < FR; ++i)
 #pragma unroll
-    for (int j = 0; j < FC; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < FC; ++j) acc[i][j] = Acc{0, 0, 0, 0};
 
   const int64_t nk = p.k / BK;
   GEP_FAST_GLOAD(0)
@@ -536,10 +558,11 @@ dgemm_fast_kernel(Params p) {
     for (int j = 0; j < FC; ++j) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t col = n0 + wc * WN + j * 16 + (lane >> 4) + 4 * r;
+        const int64_t col =
+            n0 + wc * WN + j * 16 + (F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
         if (p.uplo == 1 && row < col) continue;
         double* c = p.C + row + col * p.ldc;
-        double v = p.alpha * acc[i][j][r];
+        double v = p.alpha * (double)acc[i][j][r];
         if (p.beta != 0.0) v += p.beta * *c;
         *c = v;
       }
@@ -583,6 +606,18 @@ __global__ void splitk_reduce(int64_t m, int64_t n, int nsplit, const double* __
   C[i + j * ldc] = v;
 }
 
+template <bool F32>
+void launch_fast_kernel(const Gemm& g, const Params& p, dim3 grid, hipStream_t s) {
+  if (!g.transA && !g.transB)
+    hipLaunchKernelGGL((dgemm_fast_kernel<false, false, F32>), grid, dim3(NT), 0, s, p);
+  else if (g.transA && !g.transB)
+    hipLaunchKernelGGL((dgemm_fast_kernel<true, false, F32>), grid, dim3(NT), 0, s, p);
+  else if (!g.transA && g.transB)
+    hipLaunchKernelGGL((dgemm_fast_kernel<false, true, F32>), grid, dim3(NT), 0, s, p);
+  else
+    hipLaunchKernelGGL((dgemm_fast_kernel<true, true, F32>), grid, dim3(NT), 0, s, p);
+}
+
 void launch_fast(const Gemm& g, hipStream_t s) {
   Params p;
   p.m = g.m; p.n = g.n; p.k = g.k;
@@ -595,14 +630,14 @@ void launch_fast(const Gemm& g, hipStream_t s) {
   p.kchunk = 0;
   p.vecA = p.vecB = 1;
   dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n));
-  if (!g.transA && !g.transB)
-    hipLaunchKernelGGL((dgemm_fast_kernel<false, false>), grid, dim3(NT), 0, s, p);
-  else if (g.transA && !g.transB)
-    hipLaunchKernelGGL((dgemm_fast_kernel<true, false>), grid, dim3(NT), 0, s, p);
-  else if (!g.transA && g.transB)
-    hipLaunchKernelGGL((dgemm_fast_kernel<false, true>), grid, dim3(NT), 0, s, p);
+  // algorithmic flops: every element of C that is asked for (lower triangle with
+  // the diagonal when uplo = 1) costs 2k
+  const double elems = g.uplo == 1 ? 0.5 * (double)g.n * (double)(g.n + 1) : (double)g.m * g.n;
+  ProbeScope probe(PROBE_GEMM, s, 2.0 * (double)g.k * elems);
+  if (math_mode() == MathMode::Fp32)
+    launch_fast_kernel<true>(g, p, grid, s);
   else
-    hipLaunchKernelGGL((dgemm_fast_kernel<true, true>), grid, dim3(NT), 0, s, p);
+    launch_fast_kernel<false>(g, p, grid, s);
   GEP_LAUNCH_CHECK();
 }
 

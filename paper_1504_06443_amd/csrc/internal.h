@@ -90,4 +90,13 @@ void backward(int64_t M, const double* lam, const double* Y, int64_t ldy, const 
 // ---------------------------------------------------------------- finishing
 void sign_fix(int64_t n, int64_t ncols, double* Y, int64_t ldy, hipStream_t s);
 
+// FP64 refinement of approximate eigenvectors Y (M x M, ldy) of (A, B), lower
+// triangles of A and B read: overwrites Y and lambda with the refined,
+// ascending eigenpairs.  W1, W2: M x M scratch (leading dimension M).  Writes the
+// largest first-order coupling left between blocks to *coupling_out (device).
+size_t refine_workspace(int64_t M);
+void refine(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb, double* Y,
+            int64_t ldy, double* lambda, double* W1, double* W2, Arena& ws, double* coupling_out,
+            hipStream_t s);
+
 }  // namespace gep

@@ -1,0 +1,88 @@
+// Host-side runtime state: the per-thread GEMM arithmetic mode and the launch
+// probes (HIP event pairs around individual kernel launches).
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+
+namespace gep {
+namespace {
+
+thread_local MathMode t_mode = MathMode::Fp64;
+
+struct ProbeRecord {
+  hipEvent_t start, stop;
+  double flops;
+};
+
+std::mutex g_probe_mu;
+bool g_probe_on = false;
+std::vector<ProbeRecord> g_records[PROBE_COUNT];
+std::vector<hipEvent_t> g_free_events;
+
+hipEvent_t take_event() {
+  if (!g_free_events.empty()) {
+    hipEvent_t e = g_free_events.back();
+    g_free_events.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  GEP_HIP(hipEventCreate(&e));
+  return e;
+}
+
+}  // namespace
+
+MathMode math_mode() { return t_mode; }
+
+MathScope::MathScope(MathMode m) : saved(t_mode) { t_mode = m; }
+MathScope::~MathScope() { t_mode = saved; }
+
+void probe_enable(bool on) {
+  std::lock_guard<std::mutex> lk(g_probe_mu);
+  g_probe_on = on;
+}
+
+ProbeScope::ProbeScope(int id_, hipStream_t s_, double flops_) : id(id_), s(s_), flops(flops_) {
+  std::lock_guard<std::mutex> lk(g_probe_mu);
+  on = g_probe_on && id >= 0 && id < PROBE_COUNT;
+  if (!on) return;
+  ProbeRecord r;
+  r.start = take_event();
+  r.stop = take_event();
+  r.flops = flops;
+  GEP_HIP(hipEventRecord(r.start, s));
+  g_records[id].push_back(r);
+}
+
+ProbeScope::~ProbeScope() {
+  if (!on) return;
+  std::lock_guard<std::mutex> lk(g_probe_mu);
+  // the record pushed by this scope is the last one of its kind: launches of one
+  // kind are issued one at a time from the host
+  hipEventRecord(g_records[id].back().stop, s);
+}
+
+bool probe_read(int id, int64_t* launches, double* ms, double* flops) {
+  if (id < 0 || id >= PROBE_COUNT) return false;
+  std::lock_guard<std::mutex> lk(g_probe_mu);
+  int64_t n = 0;
+  double t = 0.0, f = 0.0;
+  for (const ProbeRecord& r : g_records[id]) {
+    GEP_HIP(hipEventSynchronize(r.stop));
+    float e = 0.0f;
+    GEP_HIP(hipEventElapsedTime(&e, r.start, r.stop));
+    t += e;
+    f += r.flops;
+    ++n;
+    g_free_events.push_back(r.start);
+    g_free_events.push_back(r.stop);
+  }
+  g_records[id].clear();
+  if (launches) *launches = n;
+  if (ms) *ms = t;
+  if (flops) *flops = f;
+  return true;
+}
+
+}  // namespace gep

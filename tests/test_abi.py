@@ -68,6 +68,7 @@ def _solve(lib, M, lda=None, A=FAKE, B=FAKE, lam=FAKE, Y=FAKE, job=1, prec=0, ws
     (dict(M=10, Y=P(0)), 7),
     (dict(M=10, job=5), 9),
     (dict(M=10, prec=7), 10),
+    (dict(M=10, job=0, prec=1), 10),  # mixed precision refines eigenvectors: vectors only
     (dict(M=10, ws=P(0x200010)), 11),
     (dict(M=10, info=P(0)), 13),
 ])
@@ -96,3 +97,25 @@ def test_phase_entry_points_validate(lib):
     assert lib.gep_last_bad_arg() == 6
     assert lib.gep_band_reduce(5, FAKE, 5, 65, FAKE, 70, FAKE, 1 << 30, None) == -1
     assert lib.gep_last_bad_arg() == 4
+
+
+def test_mixed_workspace_is_larger(lib):
+    assert lib.gep_workspace_size(1000, 1, 1) > lib.gep_workspace_size(1000, 1, 0)
+
+
+def test_dgemm_rejects_bad_arguments(lib):
+    def call(ta=0, tb=0, uplo=0, m=4, n=4, k=4, lda=4, ldb=4, ldc=4, arith=0):
+        return lib.gep_dgemm(ta, tb, uplo, m, n, k, 1.0, FAKE, lda, FAKE, ldb, 0.0, FAKE, ldc,
+                             arith, None)
+    for kw, idx in [(dict(ta=2), 1), (dict(tb=-1), 2), (dict(uplo=1, n=5, ldb=4), 3),
+                    (dict(m=-1), 4), (dict(lda=3), 9), (dict(ldc=3), 14), (dict(arith=2), 15)]:
+        assert call(**kw) == -1, kw
+        assert lib.gep_last_bad_arg() == idx, kw
+
+
+def test_probe_names_and_bad_index(lib):
+    assert lib.gep_probe_name(0) == b"dgemm_fast_kernel"
+    assert lib.gep_probe_name(1) == b"q2_apply"
+    assert lib.gep_probe_name(4) is None
+    assert lib.gep_probe_read(4, None, None, None) == -1
+    assert lib.gep_last_bad_arg() == 1

@@ -26,7 +26,7 @@ def _run(ta, tb, uplo, m, n, k, alpha, beta, off=0, seed=0):
     dC = torch.from_numpy(C.ravel().copy()).cuda()
     P = lambda t, o=0: ctypes.c_void_p(t.data_ptr() + 8 * o)
     st = lib().gep_dgemm(ta, tb, uplo, m, n, k, alpha, P(dA, off), lda, P(dB, off), ldb, beta,
-                         P(dC), ldc, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+                         P(dC), ldc, 0, ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
     assert st == 0
     out = dC.cpu().numpy().reshape(n, ldc)[:, :m].T
     Am = A[:, :Ar].T
@@ -54,3 +54,41 @@ def test_dgemm_lower_only(gpu):
     say("[gemm] lower only")
     out, ref, k = _run(0, 1, 1, 300, 300, 77, -1.0, 1.0)
     assert np.abs(out - ref).max() <= 1e-14 * k * 4
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_gemm_fp32_arithmetic(gpu, ta, tb):
+    """arith = 1: interior tiles multiply FP32-rounded operands with FP32
+    accumulation.  Bound: |C - fl32(A) fl32(B)| <= gamma_k |fl32(A)| |fl32(B)|
+    elementwise, gamma_k = k u / (1 - k u), u = 2^-24 (standard dot-product error
+    bound); the FP64 edge strips meet it trivially."""
+    import torch
+    from paper_1504_06443_amd._binding import lib
+    rng = np.random.default_rng(11 + 2 * ta + tb)
+    m, n, k = 1100, 1800, 520  # >= 128 tiles of 128 x 128: interior kernel + strips
+    Ar, Ac = (k, m) if ta else (m, k)
+    Br, Bc = (n, k) if tb else (k, n)
+    A = rng.standard_normal((Ac, Ar))   # column-major Ar x Ac held as rows of length Ar
+    B = rng.standard_normal((Bc, Br))
+    dA, dB = torch.from_numpy(A.ravel().copy()).cuda(), torch.from_numpy(B.ravel().copy()).cuda()
+    dC = torch.zeros(n * m, dtype=torch.float64, device="cuda")
+    P = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = lib().gep_dgemm(ta, tb, 0, m, n, k, 1.0, P(dA), Ar, P(dB), Br, 0.0, P(dC), m, 1,
+                         ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0
+    out = dC.cpu().numpy().reshape(n, m).T
+    A32 = A.astype(np.float32).astype(np.float64).T
+    B32 = B.astype(np.float32).astype(np.float64).T
+    opA = A32.T if ta else A32
+    opB = B32.T if tb else B32
+    ref = opA @ opB
+    u = 2.0 ** -24
+    gamma = k * u / (1 - k * u)
+    bound = gamma * (np.abs(opA) @ np.abs(opB))
+    assert np.all(np.abs(out - ref) <= bound)
+    # and it is not FP64 arithmetic on the interior: the error is FP32-sized there
+    assert np.abs(out - ref)[:1024, :1792].max() > 1e-10
+    # the bottom strip stays FP64 on the unrounded operands
+    A64, B64 = A.T, B.T
+    ref64 = (A64.T if ta else A64) @ (B64.T if tb else B64)
+    assert np.abs(out - ref64)[1024:, :].max() <= 1e-12 * np.abs(ref64).max()
