@@ -86,6 +86,85 @@ def kernel_traffic(kernel: str, workload: str):
     return float(fields["bytes_per_launch"])
 
 
+def batched_extension(gep, torch, replays: int = 5) -> dict:
+    """The 256-instance batch (orders log-uniform in [64, 2048], instance seeds
+    4000+i), FP64 with vectors, one gep_solve_batched call captured in a HIP graph;
+    replay time (median) -> solves/s and algorithmic TFLOP/s."""
+    import synth
+    sizes = synth.batch_sizes()
+    bs = gep.BatchedSolver(sizes)
+    As, Bs = [], []
+    for i, M in enumerate(sizes):
+        A, B = synth.batch_instance(i, M)
+        As.append(torch.from_numpy(A))
+        Bs.append(torch.from_numpy(B))
+    bs.load([a.cuda() for a in As], [b.cuda() for b in Bs])
+    del As, Bs
+    bs.run()
+    torch.cuda.synchronize()
+    ref = [l.clone() for l, _ in bs.results()]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        bs.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.graph(g, stream=s):
+            bs.run()
+        t_capture = time.perf_counter() - t0
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(replays):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.replay()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    same = all(torch.equal(l, l0) for (l, _), l0 in zip(bs.results(), ref))
+    T = sorted(times)[len(times) // 2]
+    flops = sum(alg_flops(M) for M in sizes)
+    print(f"[bench] batched: replay {T * 1e3:.1f} ms ({len(sizes)} solves)", file=sys.stderr,
+          flush=True)
+    return {"workload": "batch256_logu64_2048_seed4", "instances": len(sizes),
+            "replay_ms_median": T * 1e3, "solves_per_s": len(sizes) / T,
+            "tflops_fp64": flops / T / 1e12, "capture_ms": t_capture * 1e3,
+            "replays_equal_eager": bool(same)}
+
+
+def adjoint_extension(gep, torch) -> dict:
+    """The M = 4096 gradient workload: forward solve through GEPFunction and the
+    backward of L = sum of the lower half of the eigenvalues + tr(G Y_occ Y_occ^T)."""
+    import numpy as np
+    import synth
+    A, B = synth.workload("m4096_grad")
+    M = A.shape[0]
+    G = torch.from_numpy(synth.symmetric_normal(M, 5001, 1.0 / np.sqrt(M))).cuda()
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    tf, tb = [], []
+    for _ in range(3):
+        Ad = dA.clone().requires_grad_(True)
+        Bd = dB.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lam, Y = gep.GEPFunction.apply(Ad, Bd)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        Yo = Y[:, : M // 2]
+        L = lam[: M // 2].sum() + (G * (Yo @ Yo.t())).sum()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        tf.append(t1 - t0)
+        tb.append(t3 - t2)
+    return {"workload": "m4096_grad", "forward_ms": 1e3 * sorted(tf)[1],
+            "backward_ms": 1e3 * sorted(tb)[1],
+            "note": "backward = loss autograd (torch) + gep_backward"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +175,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the batched and adjoint measurements after the timed steps")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of known size (2 GiB read, 2 GiB "
                          "written per launch, 3 launches), the reference for scaling HBM "
@@ -231,6 +312,14 @@ def main() -> int:
         if check is not None:
             check["mixed"] = invariants(lam_m, Y)
 
+    extensions = None
+    if not args.no_extensions:
+        del Y
+        torch.cuda.empty_cache()
+        extensions = {"batched": batched_extension(gep, torch),
+                      "adjoint": adjoint_extension(gep, torch)}
+        torch.cuda.empty_cache()
+
     out = {
         "metric": METRIC,
         "value": solves_per_s,
@@ -252,6 +341,7 @@ def main() -> int:
         "mixed_speedup": mixed["speedup"] if mixed else None,
         "mixed": mixed,
         "roofline": roofline,
+        "extensions": extensions,
         "check": check,
     }
     if not args.no_cpu_baseline:

@@ -1,0 +1,62 @@
+"""GPU parity at the benchmark's full sizes: the 8192 (decay 32, seed 2) and
+32768 (decay 64, seed 3) workloads, FP64 and mixed precision, in the launch
+configuration the benchmark times (one gep_solve on the current stream).
+
+Eigenvalues are compared with the CPU oracle's, stored by
+tests/golden/make_golden.py (which calls only oracle/); eigenvectors through the
+invariants A Y = B Y Lambda and Y^T B Y = I, evaluated at full size with torch
+FP64 matmuls on the GPU (independent of libgep)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from tests.gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+TOL_LAMBDA = 1e-11
+BARS = {"fp64": (1e-12, 1e-12), "mixed": (1e-7, 1e-5)}  # (residual, B-orthogonality)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["m8192", "m32768"])
+def test_workload_against_stored_oracle(gpu, name, prec):
+    import torch
+    import paper_1504_06443_amd as gep
+    path = os.path.join(GOLDEN, f"{name}_eigenvalues.npy")
+    if not os.path.exists(path):
+        pytest.skip(f"stored oracle eigenvalues for {name} not generated "
+                    f"(python tests/golden/make_golden.py {name})")
+    ref = np.load(path)
+    meta = json.load(open(os.path.join(GOLDEN, f"{name}.json")))
+    say(f"[workload] {name} {prec}: generating")
+    A, B = synth.workload(name)
+    dA = torch.from_numpy(A).to("cuda:0")
+    dB = torch.from_numpy(B).to("cuda:0")
+    del A, B
+    n1 = meta["norm1_A"]
+    say(f"[workload] {name} {prec}: solving")
+    lam, Y = gep.solve(dA, dB, prec=prec)
+    torch.cuda.synchronize()
+    err = np.abs(lam.cpu().numpy() - ref).max() / n1
+    with torch.no_grad():
+        Yc = Y.contiguous()
+        del Y
+        BY = dB @ Yc
+        R = dA @ Yc
+        R -= BY * lam[None, :]
+        res = (R.abs().sum(0).max() / (n1 * Yc.abs().sum(0).max())).item()
+        del R
+        G = Yc.t() @ BY
+        G.diagonal().sub_(1.0)
+        orth = G.abs().max().item()
+        del G, BY, Yc
+    torch.cuda.empty_cache()
+    say(f"  |dlambda|/|A|_1 {err:.2e}  residual {res:.2e}  B-orthogonality {orth:.2e}")
+    assert err <= TOL_LAMBDA
+    assert res <= BARS[prec][0]
+    assert orth <= BARS[prec][1]
