@@ -239,6 +239,36 @@ __global__ void pack_vw(int64_t n, int w, const double* __restrict__ V, int64_t 
   WV[i + (int64_t)(w + c) * n] = v;
 }
 
+// Combined update of a panel pair (p, p+1) on the trailing matrix of p+1:
+//   VW4 = [V_p | W_p | V_q | W_q],  WV4 = [W_p | V_p | W_q | V_q]   (n1 x 2w + 2w1, ld n1)
+// with V_p, W_p taken from rows off.. of the packed VW of panel p (ld n).
+__global__ void pack_vw2(int64_t n1, int w, int w1, int64_t off, const double* __restrict__ VWp,
+                         int64_t n, const double* __restrict__ Vq, int64_t ldv,
+                         const double* __restrict__ Wq, double* __restrict__ VW4,
+                         double* __restrict__ WV4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n1) return;
+  const int c = blockIdx.y;  // 0 .. 2w + 2w1 - 1
+  double vw, wv;
+  if (c < w) {
+    vw = VWp[off + i + (int64_t)c * n];            // V_p
+    wv = VWp[off + i + (int64_t)(w + c) * n];      // W_p
+  } else if (c < 2 * w) {
+    vw = VWp[off + i + (int64_t)c * n];            // W_p
+    wv = VWp[off + i + (int64_t)(c - w) * n];      // V_p
+  } else if (c < 2 * w + w1) {
+    const int cc = c - 2 * w;
+    vw = Vq[i + (int64_t)cc * ldv];
+    wv = Wq[i + (int64_t)cc * n1];
+  } else {
+    const int cc = c - 2 * w - w1;
+    vw = Wq[i + (int64_t)cc * n1];
+    wv = Vq[i + (int64_t)cc * ldv];
+  }
+  VW4[i + (int64_t)c * n1] = vw;
+  WV4[i + (int64_t)c * n1] = wv;
+}
+
 size_t panel_lds() { return sizeof(double) * 256 * (MAXB + 1); }
 
 // Largest grid of panel_qr_coop whose workgroups are all resident at once.
@@ -265,8 +295,9 @@ size_t sy2sb_workspace(int64_t n, int b) {
   size_t e = 0;
   e += 2 * nb;               // X, X2
   e += 4 * nb;               // VW, WV
-  e += 4 * (size_t)b * b;    // G, Y, Ws, tau
-  e += splitk_work_elems(b, b, n) + 64;
+  e += 8 * nb;               // VW4, WV4 (panel pairs)
+  e += 6 * (size_t)b * b;    // G, Y, Ws, tau, U (2b x b)
+  e += splitk_work_elems(2 * b, b, n) + 64;
   e += 2 * 512 * MAXB + 2 * MAXB;  // partials, top row
   return e * sizeof(double) + (cdiv(n, b) + 1) * sizeof(unsigned) + 16 * 256;
 }
@@ -279,11 +310,14 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
   double* X2 = ws.take<double>((size_t)N * b);
   double* VW = ws.take<double>((size_t)N * 2 * b);
   double* WV = ws.take<double>((size_t)N * 2 * b);
+  double* VW4 = ws.take<double>((size_t)N * 4 * b);
+  double* WV4 = ws.take<double>((size_t)N * 4 * b);
   double* G = ws.take<double>((size_t)b * b);
   double* Y = ws.take<double>((size_t)b * b);
   double* Ws = ws.take<double>((size_t)b * b);
+  double* U = ws.take<double>((size_t)2 * b * b);
   double* tau = ws.take<double>((size_t)b);
-  const size_t skw = splitk_work_elems(b, b, N) + 64;
+  const size_t skw = splitk_work_elems(2 * b, b, N) + 64;
   double* skbuf = ws.take<double>(skw);
   double* part = ws.take<double>(2 * 512 * MAXB);
   double* top = ws.take<double>(2 * MAXB);
@@ -300,22 +334,20 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
   if (rate_khz <= 0) rate_khz = 100000;
   const uint64_t timeout_ticks = (uint64_t)rate_khz * 1000ull * 10ull;
 
-  for (int64_t col0 = 0; col0 < N; col0 += b) {
-    const int w = (int)((N - col0) < b ? (N - col0) : b);
+  // Diagonal block of the panel at col0 into the band, then the QR of the n x w
+  // panel below it (reflectors stay in place, R goes to the band) and its T.
+  auto factor = [&](int64_t col0, int w, int64_t n) {
     hipLaunchKernelGGL(diag_to_band, dim3(w), dim3(64), 0, s, (const double*)r.C, r.ldc, col0, w,
                        r.band, r.ldband);
     GEP_LAUNCH_CHECK();
-    const int64_t p0 = col0 + b;
-    const int64_t n = N - p0;
-    if (n <= 0) break;
-    double* P = r.C + p0 + col0 * r.ldc;
+    double* P = r.C + (col0 + b) + col0 * r.ldc;
     const int kmax = (int)(n < w ? n : w);
     {
-      const int G = (int)cdiv(n, 256) < coop_max ? (int)cdiv(n, 256) : coop_max;
+      const int Gn = (int)cdiv(n, 256) < coop_max ? (int)cdiv(n, 256) : coop_max;
       PanelArgs pa;
       pa.n = n; pa.w = w; pa.kmax = kmax; pa.P = P; pa.ld = r.ldc; pa.part = part; pa.top = top;
       pa.bar = bar + (col0 / b); pa.tau = tau; pa.band = r.band; pa.ldband = r.ldband;
-      pa.col0 = col0; pa.b = b; pa.rows_per = (int)cdiv(n, G); pa.err = err;
+      pa.col0 = col0; pa.b = b; pa.rows_per = (int)cdiv(n, Gn); pa.err = err;
       pa.timeout_ticks = timeout_ticks;
       if (pa.rows_per > 256) throw HipError{hipErrorInvalidValue, "panel too tall"};
       // Householder QR of an n x kmax panel: 2 n kmax^2 - 2 kmax^3 / 3 flops
@@ -323,13 +355,13 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
                        2.0 * (double)n * kmax * kmax - 2.0 * (double)kmax * kmax * kmax / 3.0);
       if (r.coop) {
         void* args[] = {&pa};
-        GEP_HIP(hipLaunchCooperativeKernel((const void*)panel_qr_coop, dim3(G), dim3(NT), args,
+        GEP_HIP(hipLaunchCooperativeKernel((const void*)panel_qr_coop, dim3(Gn), dim3(NT), args,
                                            panel_lds(), s));
       } else {
         // Batched solves: plain launch (graph-capturable).  Few workgroups (G <= 8
         // for n <= 2048) per panel and at most 16 panels in flight, so the grid's
         // workgroups always find free CUs; the barrier wait is bounded in time.
-        hipLaunchKernelGGL(panel_qr_coop, dim3(G), dim3(NT), panel_lds(), s, pa);
+        hipLaunchKernelGGL(panel_qr_coop, dim3(Gn), dim3(NT), panel_lds(), s, pa);
         GEP_LAUNCH_CHECK();
       }
     }
@@ -344,14 +376,11 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
     }
     hipLaunchKernelGGL(form_t, dim3(1), dim3(256), 0, s, w, (const double*)G, (const double*)tau, T);
     GEP_LAUNCH_CHECK();
-    double* A22 = r.C + p0 + p0 * r.ldc;
-    {  // X = A22 V   (A22 symmetric, lower stored)
-      Gemm g;
-      g.symA = true;
-      g.m = n; g.n = w; g.k = n;
-      g.A = A22; g.lda = r.ldc; g.B = P; g.ldb = r.ldc; g.C = X; g.ldc = n;
-      gemm(g, s);
-    }
+  };
+  // X (n x w) holds A22 V on entry; leaves W = X T - 1/2 V (T^T V^T X T) in X2.
+  auto form_w = [&](int64_t col0, int w, int64_t n) {
+    const double* P = r.C + (col0 + b) + col0 * r.ldc;
+    const double* T = r.T + (col0 / b) * (int64_t)b * b;
     {  // X2 = X T
       Gemm g;
       g.m = n; g.n = w; g.k = w;
@@ -379,19 +408,99 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
       g.A = P; g.lda = r.ldc; g.B = Ws; g.ldb = w; g.C = X2; g.ldc = n;
       gemm(g, s);
     }
+  };
+  auto symm_v = [&](int64_t col0, int w, int64_t n) {  // X = A22 V (A22 symmetric, lower stored)
+    const int64_t p0 = col0 + b;
+    Gemm g;
+    g.symA = true;
+    g.m = n; g.n = w; g.k = n;
+    g.A = r.C + p0 + p0 * r.ldc; g.lda = r.ldc;
+    g.B = r.C + p0 + col0 * r.ldc; g.ldb = r.ldc;
+    g.C = X; g.ldc = n;
+    gemm(g, s);
+  };
+
+  // Panels are taken in pairs (p, q = p + 1).  After p only q's block column is
+  // updated; q is factored against the stale trailing matrix, with its product
+  // corrected by the pending rank-2w term:
+  //   A22' = A22 - V_p W_p^T - W_p V_p^T   on rows / columns past q's block,
+  //   A22' V_q = A22 V_q - [V_p W_p] ([W_p V_p]^T V_q),
+  // and the trailing matrix gets one update of rank 2w + 2w_q instead of two.
+  for (int64_t col0 = 0; col0 < N;) {
+    const int w = (int)((N - col0) < b ? (N - col0) : b);
+    const int64_t p0 = col0 + b;
+    const int64_t n = N - p0;
+    if (n <= 0) {  // last diagonal block
+      hipLaunchKernelGGL(diag_to_band, dim3(w), dim3(64), 0, s, (const double*)r.C, r.ldc, col0,
+                         w, r.band, r.ldband);
+      GEP_LAUNCH_CHECK();
+      break;
+    }
+    factor(col0, w, n);
+    symm_v(col0, w, n);
+    form_w(col0, w, n);
+    const double* P = r.C + p0 + col0 * r.ldc;
     hipLaunchKernelGGL(pack_vw, dim3((unsigned)cdiv(n, 256), (unsigned)w), dim3(256), 0, s, n, w,
-                       (const double*)P, r.ldc, (const double*)X2, VW, WV);
+                       P, r.ldc, (const double*)X2, VW, WV);
     GEP_LAUNCH_CHECK();
-    {  // A22 -= V W^T + W V^T   (lower triangle)
+    double* A22 = r.C + p0 + p0 * r.ldc;
+    const int64_t n1 = n - b;  // trailing order after the next panel
+    if (n1 <= 0) {
+      // no second panel with rows below its block: plain rank-2w update
       Gemm g;
       g.transB = true;
       g.uplo = 1;
       g.m = n; g.n = n; g.k = 2 * w; g.alpha = -1.0; g.beta = 1.0;
       g.A = VW; g.lda = n; g.B = WV; g.ldb = n; g.C = A22; g.ldc = r.ldc;
       gemm(g, s);
+      col0 += b;
+      continue;
     }
+    {  // block column of q: A22[:, 0:b] -= [V W] [W V](0:b, :)^T
+      Gemm g;
+      g.transB = true;
+      g.m = n; g.n = b; g.k = 2 * w; g.alpha = -1.0; g.beta = 1.0;
+      g.A = VW; g.lda = n; g.B = WV; g.ldb = n; g.C = A22; g.ldc = r.ldc;
+      gemm(g, s);
+    }
+    const int64_t col1 = p0;
+    const int w1 = b;  // n1 > 0, so q has a full block
+    factor(col1, w1, n1);
+    symm_v(col1, w1, n1);
+    {  // U = [W_p V_p](b:, :)^T V_q   (2w x w1, k = n1)
+      Gemm g;
+      g.transA = true;
+      g.m = 2 * w; g.n = w1; g.k = n1;
+      g.A = WV + b; g.lda = n; g.B = r.C + (col1 + b) + col1 * r.ldc; g.ldb = r.ldc;
+      g.C = U; g.ldc = 2 * w;
+      g.work = skbuf; g.work_elems = skw;
+      gemm(g, s);
+    }
+    {  // X -= [V_p W_p](b:, :) U
+      Gemm g;
+      g.m = n1; g.n = w1; g.k = 2 * w; g.alpha = -1.0; g.beta = 1.0;
+      g.A = VW + b; g.lda = n; g.B = U; g.ldb = 2 * w; g.C = X; g.ldc = n1;
+      gemm(g, s);
+    }
+    form_w(col1, w1, n1);
+    hipLaunchKernelGGL(pack_vw2, dim3((unsigned)cdiv(n1, 256), (unsigned)(2 * w + 2 * w1)), dim3(256),
+                       0, s, n1, w, w1, (int64_t)b, (const double*)VW, n,
+                       (const double*)(r.C + (col1 + b) + col1 * r.ldc), r.ldc, (const double*)X2,
+                       VW4, WV4);
+    GEP_LAUNCH_CHECK();
+    {  // trailing matrix of q: lower triangle -= VW4 WV4^T
+      Gemm g;
+      g.transB = true;
+      g.uplo = 1;
+      g.m = n1; g.n = n1; g.k = 2 * w + 2 * w1; g.alpha = -1.0; g.beta = 1.0;
+      g.A = VW4; g.lda = n1; g.B = WV4; g.ldb = n1;
+      g.C = r.C + (col1 + b) + (col1 + b) * r.ldc; g.ldc = r.ldc;
+      gemm(g, s);
+    }
+    col0 += 2 * b;
   }
 }
+
 
 // Z <- Q1 Z, Q1 = Q_0 Q_1 ... Q_last with Q_p = I - V_p T_p V_p^T.  Panels are
 // applied in groups of QG consecutive panels, last group first: the product of a
@@ -417,41 +526,42 @@ __global__ void build_vg(int64_t ng, int b, int np, const double* __restrict__ C
   Vg[i + (int64_t)c * ng] = v;
 }
 
-// Tg from the panel T's and Gg (one workgroup; QG*b <= 256).
-__global__ void __launch_bounds__(256) form_tg(int b, int np, const double* __restrict__ Tp,
-                                               const double* __restrict__ Gg, double* __restrict__ Tg) {
+// Tg from the panel T's and Gg.  form_tg_init zeroes Tg and places the panel T's
+// on its diagonal; form_tg_block(j) then fills the block column j above the
+// diagonal, one workgroup per column c:
+//   x = Gg(0:jb, jb + 0..c) T_j(0..c, c),   Tg(0:jb, jb + c) = -Tg(0:jb, 0:jb) x.
+__global__ void form_tg_init(int b, int np, const double* __restrict__ Tp, double* __restrict__ Tg) {
   const int W = np * b;
-  const int tid = threadIdx.x;
-  __shared__ double X[(QG - 1) * 64 * 64];
-  for (int idx = tid; idx < W * W; idx += 256) Tg[idx] = 0.0;
-  __syncthreads();
-  for (int pi = 0; pi < np; ++pi) {
-    const double* T = Tp + (int64_t)pi * b * b;
-    for (int idx = tid; idx < b * b; idx += 256) {
-      const int r = idx % b, c = idx / b;
-      Tg[(pi * b + r) + (pi * b + c) * W] = T[idx];
-    }
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)W * W) return;
+  const int r = (int)(idx % W), c = (int)(idx / W);
+  double v = 0.0;
+  if (r / b == c / b) {
+    const int pi = r / b;
+    v = Tp[(int64_t)pi * b * b + (r % b) + (int64_t)(c % b) * b];
+  }
+  Tg[idx] = v;
+}
+
+__global__ void __launch_bounds__(256) form_tg_block(int b, int np, int j,
+                                                     const double* __restrict__ Tp,
+                                                     const double* __restrict__ Gg,
+                                                     double* __restrict__ Tg) {
+  const int W = np * b;
+  const int jb = j * b;
+  const int c = blockIdx.x;
+  const double* Tj = Tp + (int64_t)j * b * b;
+  __shared__ double x[(QG - 1) * MAXB];
+  for (int r = threadIdx.x; r < jb; r += 256) {
+    double acc = 0.0;
+    for (int q = 0; q <= c; ++q) acc += Gg[r + (int64_t)(jb + q) * W] * Tj[q + c * b];
+    x[r] = acc;
   }
   __syncthreads();
-  for (int j = 1; j < np; ++j) {
-    const int jb = j * b;
-    const double* Tj = Tp + (int64_t)j * b * b;
-    // X = Gg(0:jb, block j) * T_j   (jb x b)
-    for (int idx = tid; idx < jb * b; idx += 256) {
-      const int r = idx % jb, c = idx / jb;
-      double acc = 0.0;
-      for (int q = 0; q <= c; ++q) acc += Gg[r + (jb + q) * W] * Tj[q + c * b];
-      X[r + c * jb] = acc;
-    }
-    __syncthreads();
-    // Tg(0:jb, block j) = -Tg(0:jb, 0:jb) X
-    for (int idx = tid; idx < jb * b; idx += 256) {
-      const int r = idx % jb, c = idx / jb;
-      double acc = 0.0;
-      for (int q = r; q < jb; ++q) acc += Tg[r + q * W] * X[q + c * jb];
-      Tg[r + (jb + c) * W] = -acc;
-    }
-    __syncthreads();
+  for (int r = threadIdx.x; r < jb; r += 256) {
+    double acc = 0.0;
+    for (int q = r; q < jb; ++q) acc += Tg[r + (int64_t)q * W] * x[q];
+    Tg[r + (int64_t)(jb + c) * W] = -acc;
   }
 }
 
@@ -497,9 +607,17 @@ void apply_q1(const BandReduction& r, double* Z, int64_t ldz, int64_t ncols, Are
       g.work = skbuf; g.work_elems = skw;
       gemm(g, s);
     }
-    hipLaunchKernelGGL(form_tg, dim3(1), dim3(256), 0, s, b, np,
-                       (const double*)(r.T + (col0 / b) * (int64_t)b * b), (const double*)Gg, Tg);
-    GEP_LAUNCH_CHECK();
+    {
+      const double* Tp = r.T + (col0 / b) * (int64_t)b * b;
+      hipLaunchKernelGGL(form_tg_init, dim3((unsigned)cdiv(W * W, 256)), dim3(256), 0, s, b, np,
+                         Tp, Tg);
+      GEP_LAUNCH_CHECK();
+      for (int j = 1; j < np; ++j) {
+        hipLaunchKernelGGL(form_tg_block, dim3((unsigned)b), dim3(256), 0, s, b, np, j, Tp,
+                           (const double*)Gg, Tg);
+        GEP_LAUNCH_CHECK();
+      }
+    }
     {
       Gemm g;
       g.transA = true;

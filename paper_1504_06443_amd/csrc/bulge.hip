@@ -464,70 +464,120 @@ q2_apply(Q2Args a) {
   for (int idx = tid; idx < HB * ZLD; idx += NT) Zs[idx] = 0.0;
   Prefetch f;
   if (a.ngroups > 0) fetch_vt(a, a.ngroups - 1, 0, f);
-  for (int64_t j = a.ngroups - 1; j >= 0; --j) {
-    const int64_t s0 = j * NBW;
-    const int64_t base = s0 + 1;
+  // Passes over Z take two sweep groups at once, jh = jl + 1 (group 0 alone when
+  // the count is odd).  Window rows are relative to the lower group's base; the
+  // blocks run in the order (jh, 0), (jl, 0), (jh, 1), (jl, 1), ...: block (jl, t)
+  // meets only (jh, t-1) and (jh, t) among the upper group's blocks and shares no
+  // row with (jh, t+1), so this order gives the same product as the upper group
+  // followed by the lower one, while Z is streamed once per two groups.  After
+  // (jl, t), rows [t b, t b + b) are final; the live rows never exceed b + 63.
+  for (int64_t jh = a.ngroups - 1; jh >= 0; jh -= 2) {
+    const bool two = jh >= 1;
+    const int64_t jl = two ? jh - 1 : jh;
+    const int64_t base = jl * NBW + 1;
     const int64_t nrel = a.n - base;
-    const int64_t P0 = positions(a.n, b, s0);
-    // first window of the group (not prefetched: the previous group has just been
-    // written back)
+    const int64_t Pl = positions(a.n, b, jl * NBW);
+    const int64_t Ph = two ? positions(a.n, b, jh * NBW) : 0;
+    const int64_t nblk = Pl + Ph;
+    // block q of the pass: group, position, row offset in the window
+    auto decode = [&](int64_t q, int64_t& g, int64_t& t, int64_t& rb) {
+      if (q < 2 * Ph) {
+        t = q >> 1;
+        g = (q & 1) ? jl : jh;
+        rb = t * b + ((q & 1) ? 0 : NBW);
+      } else {
+        t = q - Ph;
+        g = jl;
+        rb = t * b;
+      }
+    };
+    // first window (not prefetched: the previous pass has just been written back)
+    int64_t loaded;
     __syncthreads();
     {
-      const int64_t hi = Hfull < nrel ? Hfull : nrel;
+      int64_t g0, t0, rb0;
+      decode(0, g0, t0, rb0);
+      const int64_t hi = (rb0 + Hfull) < nrel ? (rb0 + Hfull) : nrel;
       for (int64_t lo = 0; lo < hi; lo += MAXB) {
         Prefetch g;
         const int64_t h2 = (lo + MAXB) < hi ? (lo + MAXB) : hi;
         fetch_rows(a, base, lo, h2, c0, ncol, g);
         commit_rows(g, lo, h2, Zs);
       }
+      loaded = hi;
     }
-    for (int64_t k = 0; k < P0; ++k) {
-      const int64_t kb = k * b;
+    int64_t pend_lo = 0, pend_hi = 0;  // prefetched rows not yet in the window
+    for (int64_t q = 0; q < nblk; ++q) {
+      int64_t gq, tq, kb;
+      decode(q, gq, tq, kb);
       __syncthreads();  // the previous block's write-back frees the slots refilled here
       commit_vt(f, Vs, Tt);
-      if (k > 0) {
-        int64_t lo = kb - b + Hfull, hi = kb + Hfull;
-        if (hi > nrel) hi = nrel;
-        commit_rows(f, lo, hi, Zs);
+      if (pend_hi > pend_lo) {
+        commit_rows(f, pend_lo, pend_hi, Zs);
+        loaded = pend_hi;
+        pend_lo = pend_hi = 0;
       }
       __syncthreads();
-      // prefetch block k+1 (or the next group's first block)
-      if (k + 1 < P0) {
-        fetch_vt(a, j, k + 1, f);
-        int64_t lo = kb + Hfull, hi = kb + b + Hfull;
+      // prefetch the next block (or the next pass's first block)
+      if (q + 1 < nblk) {
+        int64_t gn, tn, rbn;
+        decode(q + 1, gn, tn, rbn);
+        fetch_vt(a, gn, tn, f);
+        int64_t hi = rbn + Hfull;
         if (hi > nrel) hi = nrel;
-        if (hi > lo) fetch_rows(a, base, lo, hi, c0, ncol, f);
-      } else if (j > 0) {
-        fetch_vt(a, j - 1, 0, f);
+        if (hi > loaded) {
+          fetch_rows(a, base, loaded, hi, c0, ncol, f);
+          pend_lo = loaded;
+          pend_hi = hi;
+        }
+      } else if (jl > 0) {
+        fetch_vt(a, jl - 1, 0, f);
       }
-      // W1^T (SWA x NBW) = Z_w^T V, tile (ti, tj)
+      // W1^T (SWA x NBW) = Z_w^T V, tile (ti, tj).  Reflector c of the block is
+      // supported on rows [c, c + b) of the window, so tile tj only needs rows
+      // [16 tj, 16 tj + 15 + b); two accumulator chains (even / odd k steps).
       {
-        v4d w = {0.0, 0.0, 0.0, 0.0};
-        for (int ks = 0; ks < KS1; ++ks) {
-          const int row = ks * 4 + (lane >> 4);
-          const int slot = (int)((kb + row) & (HB - 1));
-          const double av = Zs[slot * ZLD + ti * 16 + (lane & 15)];
-          const double bv = Vs[row * VLD + tj * 16 + (lane & 15)];
-          w = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, w, 0, 0, 0);
+        const int ks_lo = 4 * tj;
+        int ks_hi = (16 * tj + 15 + b + 3) / 4;
+        if (ks_hi > KS1) ks_hi = KS1;
+        v4d w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+        int ks = ks_lo;
+        for (; ks + 1 < ks_hi; ks += 2) {
+          const int row0 = ks * 4 + (lane >> 4), row1 = row0 + 4;
+          const double a0 = Zs[(int)((kb + row0) & (HB - 1)) * ZLD + ti * 16 + (lane & 15)];
+          const double b0 = Vs[row0 * VLD + tj * 16 + (lane & 15)];
+          const double a1 = Zs[(int)((kb + row1) & (HB - 1)) * ZLD + ti * 16 + (lane & 15)];
+          const double b1 = Vs[row1 * VLD + tj * 16 + (lane & 15)];
+          w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, w0, 0, 0, 0);
+          w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, w1, 0, 0, 0);
+        }
+        if (ks < ks_hi) {
+          const int row0 = ks * 4 + (lane >> 4);
+          const double a0 = Zs[(int)((kb + row0) & (HB - 1)) * ZLD + ti * 16 + (lane & 15)];
+          const double b0 = Vs[row0 * VLD + tj * 16 + (lane & 15)];
+          w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, w0, 0, 0, 0);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = w[r];
+          Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = w0[r] + w1[r];
       }
       __syncthreads();
-      // W2^T = W1^T T^T, tile (ti, tj)
-      v4d u = {0.0, 0.0, 0.0, 0.0};
+      // W2^T = W1^T T^T, tile (ti, tj), two chains
+      v4d u0 = {0.0, 0.0, 0.0, 0.0}, u1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int ks = 0; ks < NBW / 4; ++ks) {
-        const int kk = ks * 4 + (lane >> 4);
-        const double av = Ws[(ti * 16 + (lane & 15)) * VLD + kk];
-        const double bv = Tt[kk * VLD + tj * 16 + (lane & 15)];
-        u = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, u, 0, 0, 0);
+      for (int ks = 0; ks < NBW / 4; ks += 2) {
+        const int k0 = ks * 4 + (lane >> 4), k1 = k0 + 4;
+        const double a0 = Ws[(ti * 16 + (lane & 15)) * VLD + k0];
+        const double b0 = Tt[k0 * VLD + tj * 16 + (lane & 15)];
+        const double a1 = Ws[(ti * 16 + (lane & 15)) * VLD + k1];
+        const double b1 = Tt[k1 * VLD + tj * 16 + (lane & 15)];
+        u0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, u0, 0, 0, 0);
+        u1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, u1, 0, 0, 0);
       }
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < 4; ++r)
-        Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = u[r];
+        Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = u0[r] + u1[r];
       __syncthreads();
       // Z_w^T -= W2^T V^T : (SWA x HP) = 2 x 6 tiles, 3 per wave (column block ti)
       {
@@ -554,10 +604,11 @@ q2_apply(Q2Args a) {
         }
       }
       __syncthreads();
-      // rows [kb, kb + b) are final for this group
-      {
+      // after a lower-group block, rows [kb, kb + b) are final for this pass; the
+      // last block writes back everything still in the window
+      if (gq == jl) {
         int64_t hi = kb + b;
-        if (k + 1 == P0) hi = nrel;  // last block: the whole remaining window
+        if (q + 1 == nblk) hi = loaded;
         if (hi > nrel) hi = nrel;
         for (int64_t lo = kb; lo < hi; lo += MAXB) {
           const int64_t h2 = (lo + MAXB) < hi ? (lo + MAXB) : hi;
@@ -626,7 +677,13 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     GEP_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
     if (rate_khz <= 0) rate_khz = 100000;
     a.timeout_ticks = (uint64_t)rate_khz * 1000ull * 10ull;  // 10 s for any single wait
-    int64_t groups = nsweeps < 512 ? nsweeps : 512;
+    // Sweep s + 1 trails sweep s by about two positions, so at most about half of
+    // a sweep's positions are ever worked on at once: more workgroups would only
+    // spin (and, in batched solves, keep other instances' chases off the CUs).
+    const int64_t npos0 = (n - 2) / c.b + 1;
+    int64_t groups = npos0 / 2 + 8;
+    if (groups > nsweeps) groups = nsweeps;
+    if (groups > 512) groups = 512;
     ProbeScope probe(PROBE_CHASE, s, 6.0 * c.b * (double)n * (double)n);
     hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(NT), 0, s, a);
     GEP_LAUNCH_CHECK();

@@ -391,10 +391,24 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
 
   // Epilogue: element r of acc[i][j] is C(row, col) with
   //   row = m0 + wr*WM + i*16 + lane%16,  col = n0 + wc*WN + j*16 + lane/16 + 4r.
+  // The old C values of one row group are all loaded before any of them is
+  // stored: interleaved load / store pairs would each wait a full memory latency
+  // (the compiler cannot prove that a store does not alias the next load).
 #pragma unroll
   for (int i = 0; i < FR; ++i) {
     const int64_t row = m0 + wr * WM + i * 16 + (lane & 15);
     if (row >= p.m) continue;
+    double cold[FC][4];
+    if (p.beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < FC; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t col = n0 + wc * WN + j * 16 + (lane >> 4) + 4 * r;
+          const bool ok = col < p.n && !(p.uplo == 1 && row < col);
+          cold[j][r] = ok ? C[row + col * p.ldc] : 0.0;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < FC; ++j) {
 #pragma unroll
@@ -402,10 +416,9 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
         const int64_t col = n0 + wc * WN + j * 16 + (lane >> 4) + 4 * r;
         if (col >= p.n) continue;
         if (p.uplo == 1 && row < col) continue;
-        double* c = C + row + col * p.ldc;
         double v = p.alpha * acc[i][j][r];
-        if (p.beta != 0.0) v += p.beta * *c;
-        *c = v;
+        if (p.beta != 0.0) v += p.beta * cold[j][r];
+        C[row + col * p.ldc] = v;
       }
     }
   }
@@ -551,9 +564,21 @@ dgemm_fast_kernel(Params p) {
 #undef GEP_FAST_LSTORE
 #undef GEP_FAST_COMPUTE
 
+  // old C values of a row group loaded together before the stores (see dgemm_tile)
 #pragma unroll
   for (int i = 0; i < FR; ++i) {
     const int64_t row = m0 + wr * WM + i * 16 + (lane & 15);
+    double cold[FC][4];
+    if (p.beta != 0.0) {
+#pragma unroll
+      for (int j = 0; j < FC; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t col =
+              n0 + wc * WN + j * 16 + (F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
+          cold[j][r] = (p.uplo == 1 && row < col) ? 0.0 : p.C[row + col * p.ldc];
+        }
+    }
 #pragma unroll
     for (int j = 0; j < FC; ++j) {
 #pragma unroll
@@ -561,10 +586,9 @@ dgemm_fast_kernel(Params p) {
         const int64_t col =
             n0 + wc * WN + j * 16 + (F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
         if (p.uplo == 1 && row < col) continue;
-        double* c = p.C + row + col * p.ldc;
         double v = p.alpha * (double)acc[i][j][r];
-        if (p.beta != 0.0) v += p.beta * *c;
-        *c = v;
+        if (p.beta != 0.0) v += p.beta * cold[j][r];
+        p.C[row + col * p.ldc] = v;
       }
     }
   }
