@@ -453,8 +453,13 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 dgemm_fast_kernel(Params p) {
   using S = typename std::conditional<F32, float, double>::type;
   using Acc = typename std::conditional<F32, v4f, v4d>::type;
-  constexpr int BM = 128, BN = 128, BK = FAST_BK, PAD = 4;
-  constexpr int LDA_S = BM + PAD, LDB_S = BN + PAD;
+  constexpr int BM = 128, BN = 128, BK = FAST_BK;
+  // LDS row strides.  An operand staged with 16-byte stores (A plain, B
+  // transposed) needs an even stride; one staged element by element lands 8
+  // lanes on rows 2p (p = 0..7) of one column, which an odd stride (129) spreads
+  // over all banks (an even one, 132, folds them onto two).
+  constexpr int LDA_S = TA ? BM + 1 : BM + 4;
+  constexpr int LDB_S = TB ? BN + 4 : BN + 1;
   constexpr int WM = 64, WN = 64, FR = 4, FC = 4;
   constexpr int PA2 = BM * BK / 2 / NT, PB2 = BN * BK / 2 / NT;
   __shared__ S As[2][BK * LDA_S];
@@ -565,11 +570,12 @@ dgemm_fast_kernel(Params p) {
 #undef GEP_FAST_COMPUTE
 
   // old C values of a row group loaded together before the stores (see dgemm_tile)
+  const double beta_epi = p.beta;
 #pragma unroll
   for (int i = 0; i < FR; ++i) {
     const int64_t row = m0 + wr * WM + i * 16 + (lane & 15);
     double cold[FC][4];
-    if (p.beta != 0.0) {
+    if (beta_epi != 0.0) {
 #pragma unroll
       for (int j = 0; j < FC; ++j)
 #pragma unroll
@@ -587,7 +593,7 @@ dgemm_fast_kernel(Params p) {
             n0 + wc * WN + j * 16 + (F32 ? 4 * (lane >> 4) + r : (lane >> 4) + 4 * r);
         if (p.uplo == 1 && row < col) continue;
         double v = p.alpha * (double)acc[i][j][r];
-        if (p.beta != 0.0) v += p.beta * cold[j][r];
+        if (beta_epi != 0.0) v += beta_epi * cold[j][r];
         p.C[row + col * p.ldc] = v;
       }
     }

@@ -72,12 +72,15 @@ def test_c5_gradient_vs_central_differences(gpu):
     L.backward()
     gA, gB = Ad.grad, Bd.grad
     h = 1e-6
-    # Noise floor of the central difference: the two solves round independently,
-    # about eps * |A|_1 per occupied eigenvalue, adding up like a random walk over
-    # the nocc terms, divided by 2h.  A direction passes if it is within 1e-4
-    # relative or within 10x that floor.
+    # Noise floor of the central difference, divided by 2h: each occupied
+    # eigenvalue of an FP64 solve is off by up to ~10 eps |A|_1 (the solver's
+    # measured |d lambda| / |A|_1 is ~2.7e-15 = 12 eps at this size), adding up
+    # like a random walk over the nocc terms; the two solves round independently
+    # (x sqrt 2) and the eigenvector term tr(G Y Y^T) carries noise of the same
+    # size (x 2): 10 * sqrt(2) * 2 ~ 30.  A direction passes if it is within 1e-4
+    # relative or within that floor.
     eps = np.finfo(np.float64).eps
-    floor = 10.0 * eps * oracle.norm1_sym_lower(A) * np.sqrt(nocc) / (2 * h)
+    floor = 30.0 * eps * oracle.norm1_sym_lower(A) * np.sqrt(nocc) / (2 * h)
     worst = 0.0
     for d in range(20):
         E = to_gpu(synth.unit_direction(M, 5100 + d))

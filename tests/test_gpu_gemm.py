@@ -92,3 +92,21 @@ def test_gemm_fp32_arithmetic(gpu, ta, tb):
     A64, B64 = A.T, B.T
     ref64 = (A64.T if ta else A64) @ (B64.T if tb else B64)
     assert np.abs(out - ref64)[1024:, :].max() <= 1e-12 * np.abs(ref64).max()
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (1, 0), (0, 1), (1, 1)])
+@pytest.mark.parametrize("alpha,beta", [(-1.0, 1.0), (1.0, 0.5), (-1.0, -2.0), (1.25, -0.5)])
+def test_dgemm_interior_kernel(gpu, ta, tb, alpha, beta):
+    """Shapes with >= 128 tiles of 128 x 128 run the interior kernel (plus k tail
+    and edge strips); alpha = +-1 with beta != 0 takes the path that starts the
+    accumulators from alpha beta C, the others the FP64 epilogue."""
+    say(f"[gemm] interior ta={ta} tb={tb} alpha={alpha} beta={beta}")
+    out, ref, kk = _run(ta, tb, 0, 1100, 1800, 520, alpha, beta, seed=3)
+    assert np.abs(out - ref).max() <= 1e-14 * kk * 4 * max(1.0, abs(beta))
+
+
+@pytest.mark.parametrize("alpha,beta", [(-1.0, 1.0), (1.0, 0.0)])
+def test_dgemm_interior_lower_only(gpu, alpha, beta):
+    say(f"[gemm] interior lower alpha={alpha} beta={beta}")
+    out, ref, k = _run(0, 1, 1, 1664, 1664, 256, alpha, beta, seed=4)
+    assert np.abs(out - ref).max() <= 1e-14 * k * 4
