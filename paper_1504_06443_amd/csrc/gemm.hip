@@ -37,6 +37,7 @@ struct Params {
   int64_t sA, sB, sC;
   int transA, transB, symA, uplo;
   int tiles_m, tiles_n;
+  int lower_grid = 0;  // 1: the grid holds only the tiles on or below the diagonal
   int64_t kchunk;  // > 0: batch index z sums k in [z*kchunk, (z+1)*kchunk) into C + z*sC
   int vecA, vecB;  // operand base 16-byte aligned and leading dimension even
 };
@@ -56,6 +57,23 @@ __device__ inline void tile_coords(int tiles_m, int tiles_n, int& tm, int& tn) {
   const int in_group = logical % per_group;
   tm = first_m + in_group % gsz;
   tn = in_group / gsz;
+}
+
+// Lower-triangle launches: the grid holds the T (T + 1) / 2 tiles on or below the
+// diagonal, numbered row by row; the workgroups of one XCD again take a
+// contiguous range, which now holds an equal share of the work (a full-grid
+// launch would hand the XCDs of the first tile rows almost nothing to do).
+__device__ inline void lower_tile_coords(int& tm, int& tn) {
+  const int nb = gridDim.x;
+  const int bid = blockIdx.x;
+  const int nfull = (nb / 8) * 8;
+  int logical = bid;
+  if (bid < nfull) logical = (bid % 8) * (nfull / 8) + bid / 8;
+  int r = (int)((sqrt(8.0 * (double)logical + 1.0) - 1.0) * 0.5);
+  while ((int64_t)r * (r + 1) / 2 > logical) --r;
+  while ((int64_t)(r + 1) * (r + 2) / 2 <= logical) ++r;
+  tm = r;
+  tn = logical - r * (r + 1) / 2;
 }
 
 template <int BM, int BK>
@@ -465,7 +483,10 @@ dgemm_fast_kernel(Params p) {
   __shared__ S As[2][BK * LDA_S];
   __shared__ S Bs[2][BK * LDB_S];
   int tm, tn;
-  tile_coords(p.tiles_m, p.tiles_n, tm, tn);
+  if (p.lower_grid)
+    lower_tile_coords(tm, tn);
+  else
+    tile_coords(p.tiles_m, p.tiles_n, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   if (p.uplo == 1 && m0 + BM - 1 < n0) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -659,7 +680,9 @@ void launch_fast(const Gemm& g, hipStream_t s) {
   p.tiles_n = (int)(g.n / 128);
   p.kchunk = 0;
   p.vecA = p.vecB = 1;
-  dim3 grid((unsigned)((int64_t)p.tiles_m * p.tiles_n));
+  p.lower_grid = (g.uplo == 1 && g.m == g.n) ? 1 : 0;
+  dim3 grid((unsigned)(p.lower_grid ? (int64_t)p.tiles_m * (p.tiles_m + 1) / 2
+                                    : (int64_t)p.tiles_m * p.tiles_n));
   // algorithmic flops: every element of C that is asked for (lower triangle with
   // the diagonal when uplo = 1) costs 2k
   const double elems = g.uplo == 1 ? 0.5 * (double)g.n * (double)(g.n + 1) : (double)g.m * g.n;
