@@ -233,6 +233,51 @@ def solve(A, B, vectors: bool = True, keep: bool = False) -> OracleResult:
                         d if keep else None, e if keep else None, norm1_sym_lower(A))
 
 
+def inertia_count(A, B, sigma: float) -> int:
+    """Number of eigenvalues of the pencil (A, B) below sigma, without solving it.
+
+    B is positive definite, so A - sigma B is congruent to C - sigma I with
+    C = L^{-1} A L^{-T} (Eq. 5), and by Sylvester's law of inertia the number of
+    negative eigenvalues of A - sigma B is #{lambda_k < sigma}.  That number is
+    read off a symmetric indefinite factorisation P (A - sigma B) P^T = U D U^T
+    (LAPACK dsytrf, Bunch-Kaufman pivoting: a library step) as the number of
+    negative eigenvalues of the block-diagonal D (1 x 1 pivots by sign, 2 x 2
+    pivots [a b; b c] by determinant and trace).  Only the lower triangles of A
+    and B are read; the work array may overwrite nothing the caller holds.
+    """
+    from scipy.linalg import lapack
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    n = A.shape[0]
+    if n == 0:
+        return 0
+    # lower triangle of A - sigma B, built column block by column block in
+    # Fortran order (symmetric inputs: the transpose view of C-ordered data)
+    W = np.empty((n, n), order="F")
+    step = 2048
+    for j0 in range(0, n, step):
+        j1 = min(n, j0 + step)
+        W[:, j0:j1] = np.tril(A[:, j0:j1], -j0) - sigma * np.tril(B[:, j0:j1], -j0)
+    lu, ipiv, info = lapack.dsytrf(W, lower=1, overwrite_a=1)
+    if info < 0:
+        raise ValueError(f"dsytrf argument {-info}")
+    neg = 0
+    k = 0
+    while k < n:
+        if ipiv[k] > 0:  # 1 x 1 pivot
+            neg += lu[k, k] < 0.0
+            k += 1
+        else:  # 2 x 2 pivot in rows / columns k, k+1 (lower storage)
+            a, b, c = lu[k, k], lu[k + 1, k], lu[k + 1, k + 1]
+            det = a * c - b * b
+            if det < 0.0:
+                neg += 1
+            elif a + c < 0.0:
+                neg += 2
+            k += 2
+    return int(neg)
+
+
 def eigvals(A, B) -> np.ndarray:
     return solve(A, B, vectors=False).lam
 

@@ -358,3 +358,23 @@ def test_batch_sizes_in_range():
     s = synth.batch_sizes()
     assert len(s) == 256 and min(s) >= 64 and max(s) <= 2048
     assert s == synth.batch_sizes()
+
+
+def test_inertia_count_matches_eigenvalues():
+    """Sylvester count at sigma between eigenvalues, and at an eigenvalue of a
+    known degenerate pencil, against the oracle's own eigenvalues."""
+    A, B = synth.banded_pair(300, 5.0, 91)
+    lam = oracle.solve(A, B, vectors=False).lam
+    for k in (0, 1, 17, 150, 299):
+        lo = lam[k - 1] if k > 0 else lam[0] - 1.0
+        sigma = 0.5 * (lo + lam[k]) if k > 0 else lam[0] - 1.0
+        assert oracle.inertia_count(A, B, sigma) == k
+    assert oracle.inertia_count(A, B, lam[-1] + 1.0) == 300
+    # A = alpha B: every eigenvalue equals alpha
+    assert oracle.inertia_count(-2.0 * B, B, -2.0 - 1e-9) == 0
+    assert oracle.inertia_count(-2.0 * B, B, -2.0 + 1e-9) == 300
+    # 2 x 2 pivots: a pencil whose A has a zero diagonal forces them
+    J = np.kron(np.eye(40), np.array([[0.0, 1.0], [1.0, 0.0]]))
+    assert oracle.inertia_count(J, np.eye(80), 0.0) == 40
+    assert oracle.inertia_count(J, np.eye(80), -1.5) == 0
+    assert oracle.inertia_count(J, np.eye(80), 1.5) == 80
