@@ -509,7 +509,7 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
 //   Tg(blocks i<j) = -Tg(0:i, 0:i-block) Gg(.., j) T_j,  Gg = Vg^T Vg,
 // so the application is three large GEMMs (K = QG*b) per group.
 namespace {
-constexpr int QG = 4;
+constexpr int QG = 8;
 
 // Vg (ng x QG*b, ld ng): panel i of the group starts at row i*b.
 __global__ void build_vg(int64_t ng, int b, int np, const double* __restrict__ C, int64_t ldc,
