@@ -103,6 +103,14 @@ def batched_extension(gep, torch, replays: int = 5) -> dict:
     bs.run()
     torch.cuda.synchronize()
     ref = [l.clone() for l, _ in bs.results()]
+    eager = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bs.run()
+        torch.cuda.synchronize()
+        eager.append(time.perf_counter() - t0)
+    Te = sorted(eager)[1]
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     g = torch.cuda.CUDAGraph()
@@ -124,11 +132,12 @@ def batched_extension(gep, torch, replays: int = 5) -> dict:
     same = all(torch.equal(l, l0) for (l, _), l0 in zip(bs.results(), ref))
     T = sorted(times)[len(times) // 2]
     flops = sum(alg_flops(M) for M in sizes)
-    print(f"[bench] batched: replay {T * 1e3:.1f} ms ({len(sizes)} solves)", file=sys.stderr,
-          flush=True)
+    print(f"[bench] batched: eager {Te * 1e3:.1f} ms, graph replay {T * 1e3:.1f} ms "
+          f"({len(sizes)} solves)", file=sys.stderr, flush=True)
     return {"workload": "batch256_logu64_2048_seed4", "instances": len(sizes),
             "replay_ms_median": T * 1e3, "solves_per_s": len(sizes) / T,
             "tflops_fp64": flops / T / 1e12, "capture_ms": t_capture * 1e3,
+            "eager_ms_median": Te * 1e3, "eager_solves_per_s": len(sizes) / Te,
             "replays_equal_eager": bool(same)}
 
 
