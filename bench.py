@@ -141,6 +141,33 @@ def batched_extension(gep, torch, replays: int = 5) -> dict:
             "replays_equal_eager": bool(same)}
 
 
+def single_extension(gep, torch, name: str, warmup: int, reps: int) -> dict:
+    """One of the smaller single-problem workloads (the 512 and 8192 ones): median
+    solve time over `reps` solves after `warmup` solves, phases, algorithmic
+    TFLOP/s."""
+    import synth
+    A, B = synth.workload(name)
+    M = A.shape[0]
+    dA = torch.from_numpy(A).cuda()
+    dB = torch.from_numpy(B).cuda()
+    for _ in range(warmup):
+        gep.solve(dA, dB, check_info=False)
+    times, phases = [], {}
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gep.solve(dA, dB, check_info=False)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        for k, v in gep.profile_read().items():
+            phases.setdefault(k, []).append(v)
+    T = sorted(times)[len(times) // 2]
+    import numpy as np
+    return {"workload": name, "M": M, "solves": reps, "median_ms": T * 1e3,
+            "solves_per_s": 1.0 / T, "tflops_fp64": alg_flops(M) / T / 1e12,
+            "phase_ms": {k: float(np.median(v)) for k, v in phases.items()}}
+
+
 def adjoint_extension(gep, torch) -> dict:
     """The M = 4096 gradient workload: forward solve through GEPFunction and the
     backward of L = sum of the lower half of the eigenvalues + tr(G Y_occ Y_occ^T)."""
@@ -325,7 +352,9 @@ def main() -> int:
     if not args.no_extensions:
         del Y
         torch.cuda.empty_cache()
-        extensions = {"batched": batched_extension(gep, torch),
+        extensions = {"m512": single_extension(gep, torch, "m512", 5, 50),
+                      "m8192": single_extension(gep, torch, "m8192", 1, 3),
+                      "batched": batched_extension(gep, torch),
                       "adjoint": adjoint_extension(gep, torch)}
         torch.cuda.empty_cache()
 
