@@ -80,7 +80,8 @@ __device__ bool grid_barrier(const PanelArgs& a, unsigned target) {
 __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
   extern __shared__ double Ps[];  // rows_per x (MAXB + 1), row-major
   __shared__ double wv[MAXB];
-  __shared__ double scal_sh, beta_sh, tau_sh;
+  __shared__ double red[NT / MAXB][MAXB];  // quarter sums of the partials
+  __shared__ double tops[MAXB];             // the panel's current top row
   constexpr int LDP = MAXB + 1;
   const int tid = threadIdx.x;
   const int G = gridDim.x, g = blockIdx.x;
@@ -116,19 +117,36 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
       for (int q = c + tid; q < w; q += NT) cst(&top[q], Ps[li * LDP + q]);
     }
     if (!grid_barrier(a, (unsigned)(G * (c + 1)))) return;
-    // every workgroup reduces the partials in the same order
-    if (tid < MAXB) {
-      const int q = tid;
-      double tot = 0.0;
-      if (q >= c && q < w)
-        for (int gg = 0; gg < G; ++gg) tot += cld(&part[(size_t)gg * MAXB + q]);
-      wv[q] = tot;  // holds sums for now
+    // Every workgroup reduces the partials in the same fixed order, so all derive
+    // the identical reflector.  Thread (quarter, q) sums partials quarter,
+    // quarter + 4, ... of column q; its remote loads are issued eight at a time (a
+    // serial chain of G remote loads per column was the panel's main cost at large
+    // G), and the quarter sums are added in LDS in a fixed order.  The top row is
+    // fetched in the same round.
+    {
+      const int q = tid & (MAXB - 1), qt = tid >> 6;
+      double s = 0.0;
+      if (q >= c && q < w) {
+        for (int gg0 = qt; gg0 < G; gg0 += 32) {
+          double v[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int gg = gg0 + 4 * k;
+            v[k] = cld(&part[(size_t)(gg < G ? gg : G - 1) * MAXB + q]);
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) s += (gg0 + 4 * k < G) ? v[k] : 0.0;
+        }
+        if (qt == 0) tops[q] = cld(&top[q]);
+      }
+      red[qt][q] = s;
     }
     __syncthreads();
-    if (tid == 0) {
-      const double x0 = cld(&top[c]);
-      const double sigma = wv[c];
-      double beta, tau, scal;
+    // reflector scalars, computed redundantly by every thread from the same values
+    double beta, tau, scal;
+    {
+      const double x0 = tops[c];
+      const double sigma = ((red[0][c] + red[1][c]) + red[2][c]) + red[3][c];
       if (sigma == 0.0) {
         beta = x0; tau = 0.0; scal = 0.0;
       } else {
@@ -137,18 +155,16 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
         tau = (beta - x0) / beta;
         scal = 1.0 / (x0 - beta);
       }
-      scal_sh = scal; beta_sh = beta; tau_sh = tau;
+      if (tid < MAXB) {
+        double wvq = 0.0;
+        if (tid > c && tid < w) {
+          const double pcj = tops[tid];
+          const double tot = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+          wvq = tau * (pcj + scal * (tot - x0 * pcj));
+        }
+        wv[tid] = wvq;
+      }
     }
-    __syncthreads();
-    const double scal = scal_sh, tau = tau_sh;
-    double wvq = 0.0;
-    if (tid > c && tid < w) {
-      const double x0 = cld(&top[c]);
-      const double pcj = cld(&top[tid]);
-      wvq = tau * (pcj + scal * (wv[tid] - x0 * pcj));
-    }
-    __syncthreads();
-    if (tid < MAXB) wv[tid] = wvq;
     __syncthreads();
     // apply H_c to the slice, store v_c
     for (int i = tid; i < nr; i += NT) {
@@ -157,7 +173,7 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
       double v;
       if (gi == c) {
         v = 1.0;
-        Ps[i * LDP + c] = beta_sh;
+        Ps[i * LDP + c] = beta;
       } else {
         v = Ps[i * LDP + c] * scal;
         Ps[i * LDP + c] = v;
