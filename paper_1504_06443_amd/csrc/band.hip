@@ -425,7 +425,9 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
       gemm(g, s);
     }
   };
-  auto symm_v = [&](int64_t col0, int w, int64_t n) {  // X = A22 V (A22 symmetric, lower stored)
+  // X = A22 V (A22 symmetric, lower stored).  Split K over the pair buffer VW4,
+  // which is idle between a trailing update and the next pair's packing.
+  auto symm_v = [&](int64_t col0, int w, int64_t n) {
     const int64_t p0 = col0 + b;
     Gemm g;
     g.symA = true;
@@ -433,6 +435,7 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
     g.A = r.C + p0 + p0 * r.ldc; g.lda = r.ldc;
     g.B = r.C + p0 + col0 * r.ldc; g.ldb = r.ldc;
     g.C = X; g.ldc = n;
+    g.work = VW4; g.work_elems = (size_t)N * 4 * b;
     gemm(g, s);
   };
 

@@ -78,7 +78,7 @@ __device__ inline void lower_tile_coords(int& tm, int& tn) {
 
 template <int BM, int BK>
 __device__ inline void load_a(const Params& p, const double* __restrict__ A, int64_t m0, int64_t k0,
-                              double* ra) {
+                              int64_t kend, double* ra) {
   constexpr int PER = BM * BK / NT;
   const int tid = threadIdx.x;
   int mode = p.transA ? 1 : 0;
@@ -93,7 +93,7 @@ __device__ inline void load_a(const Params& p, const double* __restrict__ A, int
       const int idx = tid + NT * i;
       const int64_t r = m0 + idx % BM, c = k0 + idx / BM;
       double v = 0.0;
-      if (r < p.m && c < p.k) {
+      if (r < p.m && c < kend) {
         if (mode == 2 && r < c) v = A[c + r * p.lda];
         else v = A[r + c * p.lda];
       }
@@ -104,7 +104,7 @@ __device__ inline void load_a(const Params& p, const double* __restrict__ A, int
     for (int i = 0; i < PER; ++i) {
       const int idx = tid + NT * i;
       const int64_t c = k0 + idx % BK, r = m0 + idx / BK;
-      ra[i] = (r < p.m && c < p.k) ? A[c + r * p.lda] : 0.0;
+      ra[i] = (r < p.m && c < kend) ? A[c + r * p.lda] : 0.0;
     }
   }
 }
@@ -307,9 +307,14 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
   const double* __restrict__ A = p.A + z * p.sA;
   const double* __restrict__ B = p.B + z * p.sB;
   double* __restrict__ C = p.C + z * p.sC;
+  // ka: absolute k of this tile's first k step.  A symmetric A is addressed with
+  // absolute k (its diagonal decides between the stored and the mirrored read), so
+  // under split-K it stays unshifted and ka carries the chunk start instead.
+  int64_t ka = 0;
   if (p.kchunk > 0) {
     const int64_t kb = z * p.kchunk;
-    A = p.A + (p.transA ? kb : kb * p.lda);
+    if (p.symA) ka = kb;
+    else A = p.A + (p.transA ? kb : kb * p.lda);
     B = p.B + (p.transB ? kb * p.ldb : kb);
     int64_t kl = p.k - kb;
     p.k = kl < p.kchunk ? kl : p.kchunk;
@@ -333,13 +338,13 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
   auto mode_of = [&](int64_t kt) -> int {
     if (!fast || kt >= nk_full) return 2;
     if (!p.symA) return p.transA ? 1 : 0;
-    const int64_t k0 = kt * BK;
+    const int64_t k0 = ka + kt * BK;
     if (m0 >= k0 + BK - 1) return 0;
     if (m0 + BM - 1 < k0) return 1;
     return FAST ? 3 : 2;
   };
   auto a_ptr = [&](int mode, int64_t kt) -> const double* {
-    const int64_t k0 = kt * BK;
+    const int64_t k0 = ka + kt * BK;
     return mode == 1 ? A + k0 + m0 * p.lda : A + m0 + k0 * p.lda;
   };
   auto b_ptr = [&](int64_t kt) -> const double* {
@@ -354,14 +359,14 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
       IO::load(p, false, a_ptr(0, 0), b_ptr(0), ra, rb);  // B part; A part replaced below
       IO::store(p, false, ra, rb, As[0], Bs[0]);
       __syncthreads();
-      sym_diag_to_lds<BM, BK, LDA_S>(p, A, m0, 0, As[0]);
+      sym_diag_to_lds<BM, BK, LDA_S>(p, A, m0, ka, As[0]);
     } else if (FAST || mode != 2) {
       IO::load(p, mode == 1, a_ptr(mode, 0), b_ptr(0), ra, rb);
       IO::store(p, mode == 1, ra, rb, As[0], Bs[0]);
     } else {
-      load_a<BM, BK>(p, A, m0, 0, ra);
+      load_a<BM, BK>(p, A, m0, ka, ka + p.k, ra);
       load_b<BN, BK>(p, B, 0, n0, rb);
-      store_a<BM, BK, LDA_S>(p, m0, 0, ra, As[0]);
+      store_a<BM, BK, LDA_S>(p, m0, ka, ra, As[0]);
       store_b<BN, BK, LDB_S>(p, rb, Bs[0]);
     }
   }
@@ -393,14 +398,14 @@ __device__ inline void dgemm_tile(Params& p, int tm, int tn, int64_t z) {
       if (FAST && nmode == 3) {
         IO::store(p, false, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
         __syncthreads();
-        sym_diag_to_lds<BM, BK, LDA_S>(p, A, m0, (kt + 1) * BK, As[buf ^ 1]);
+        sym_diag_to_lds<BM, BK, LDA_S>(p, A, m0, ka + (kt + 1) * BK, As[buf ^ 1]);
       } else if (FAST || nmode != 2) {
         IO::store(p, nmode == 1, ra, rb, As[buf ^ 1], Bs[buf ^ 1]);
       } else {
         // edge / unaligned / diagonal-straddling tile: checked loads, not prefetched
-        load_a<BM, BK>(p, A, m0, (kt + 1) * BK, ra);
+        load_a<BM, BK>(p, A, m0, ka + (kt + 1) * BK, ka + p.k, ra);
         load_b<BN, BK>(p, B, (kt + 1) * BK, n0, rb);
-        store_a<BM, BK, LDA_S>(p, m0, (kt + 1) * BK, ra, As[buf ^ 1]);
+        store_a<BM, BK, LDA_S>(p, m0, ka + (kt + 1) * BK, ra, As[buf ^ 1]);
         store_b<BN, BK, LDB_S>(p, rb, Bs[buf ^ 1]);
       }
     }
@@ -707,6 +712,20 @@ int choose_split(int64_t m, int64_t n, int64_t k) {
   return sp < 2 ? 1 : (int)sp;
 }
 
+// Symmetric-operand products here are tall and skinny (C = A22 V, n = band width,
+// k = m): m / 64 tiles of K = m each leave the CUs unevenly loaded.  Split K so the
+// launch has about 1024 workgroups, limited by the scratch the caller passes.
+int choose_split_sym(int64_t m, int64_t n, int64_t k, size_t work_elems) {
+  const int64_t tiles = cdiv(m, 64) * cdiv(n, 64);
+  int64_t sp = cdiv(1024, tiles);
+  const int64_t by_k = k / KCHUNK_MIN;
+  if (sp > by_k) sp = by_k;
+  const int64_t by_work = (int64_t)(work_elems / ((size_t)m * (size_t)n));
+  if (sp > by_work) sp = by_work;
+  if (sp > MAX_SPLIT) sp = MAX_SPLIT;
+  return sp < 2 ? 1 : (int)sp;
+}
+
 }  // namespace
 
 void gemm_grouped(const GemmDesc* desc, int count, int64_t max_m, int64_t max_n, hipStream_t s) {
@@ -723,8 +742,9 @@ size_t splitk_work_elems(int64_t m, int64_t n, int64_t k) {
 void gemm(const Gemm& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0) return;
   if (g.k <= 0 && g.beta == 1.0) return;
-  if (g.work && g.batch == 1 && !g.symA && g.uplo == 0) {
-    const int sp = choose_split(g.m, g.n, g.k);
+  if (g.work && g.batch == 1 && g.uplo == 0) {
+    const int sp = g.symA ? choose_split_sym(g.m, g.n, g.k, g.work_elems)
+                          : choose_split(g.m, g.n, g.k);
     if (sp > 1 && g.work_elems >= (size_t)sp * g.m * g.n) {
       const int64_t kc = round_up(cdiv(g.k, sp), 16);
       const int nsplit = (int)cdiv(g.k, kc);

@@ -53,7 +53,8 @@ def _band_to_dense(band, M):
     return T
 
 
-@pytest.mark.parametrize("M,b", [(3, 16), (40, 16), (100, 16), (300, 32), (333, 64), (700, 64)])
+@pytest.mark.parametrize("M,b", [(3, 16), (40, 16), (100, 16), (300, 32), (333, 64), (700, 64),
+                                 (1600, 64)])
 def test_band_reduce_preserves_spectrum(gpu, M, b):
     say(f"[band] M={M} b={b}")
     A, B = synth.banded_pair(M, 6.0, 300 + M)
