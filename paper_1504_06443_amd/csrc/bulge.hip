@@ -454,7 +454,8 @@ q2_apply(Q2Args a) {
   __shared__ double Tt[NBW * VLD];       // T^T[k][j]
   __shared__ double Zs[HB * ZLD];        // Z[slot][col]
   __shared__ double Ws[SWA * VLD];       // W1^T, then W2^T  [col][c]
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: scalar loop control
   const int ti = wave >> 1, tj = wave & 1;  // this wave's 16 x 16 tile of W (cols, c)
   const int b = a.b;
   const int64_t c0 = (int64_t)blockIdx.x * SWA;
@@ -535,28 +536,32 @@ q2_apply(Q2Args a) {
       }
       // W1^T (SWA x NBW) = Z_w^T V, tile (ti, tj).  Reflector c of the block is
       // supported on rows [c, c + b) of the window, so tile tj only needs rows
-      // [16 tj, 16 tj + 15 + b); two accumulator chains (even / odd k steps).
+      // [16 tj, 16 tj + 15 + b); two accumulator chains (even / odd k steps).  The
+      // loop is software pipelined: the LDS operands of the next two k steps are
+      // read while the MFMAs of the current two run (reads past the last step stay
+      // inside the window and V's rows, and are not used).
       {
         const int ks_lo = 4 * tj;
         int ks_hi = (16 * tj + 15 + b + 3) / 4;
         if (ks_hi > KS1) ks_hi = KS1;
+        const double* zcol = Zs + ti * 16 + (lane & 15);
+        const double* vcol = Vs + tj * 16 + (lane & 15);
+        auto zat = [&](int ks) { return zcol[(int)((kb + ks * 4 + (lane >> 4)) & (HB - 1)) * ZLD]; };
+        auto vat = [&](int ks) {
+          const int row = ks * 4 + (lane >> 4);
+          return vcol[(row < HP ? row : HP - 1) * VLD];
+        };
         v4d w0 = {0.0, 0.0, 0.0, 0.0}, w1 = {0.0, 0.0, 0.0, 0.0};
+        double a0 = zat(ks_lo), b0 = vat(ks_lo), a1 = zat(ks_lo + 1), b1 = vat(ks_lo + 1);
         int ks = ks_lo;
         for (; ks + 1 < ks_hi; ks += 2) {
-          const int row0 = ks * 4 + (lane >> 4), row1 = row0 + 4;
-          const double a0 = Zs[(int)((kb + row0) & (HB - 1)) * ZLD + ti * 16 + (lane & 15)];
-          const double b0 = Vs[row0 * VLD + tj * 16 + (lane & 15)];
-          const double a1 = Zs[(int)((kb + row1) & (HB - 1)) * ZLD + ti * 16 + (lane & 15)];
-          const double b1 = Vs[row1 * VLD + tj * 16 + (lane & 15)];
+          const double na0 = zat(ks + 2), nb0 = vat(ks + 2);
+          const double na1 = zat(ks + 3), nb1 = vat(ks + 3);
           w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, w0, 0, 0, 0);
           w1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, w1, 0, 0, 0);
+          a0 = na0; b0 = nb0; a1 = na1; b1 = nb1;
         }
-        if (ks < ks_hi) {
-          const int row0 = ks * 4 + (lane >> 4);
-          const double a0 = Zs[(int)((kb + row0) & (HB - 1)) * ZLD + ti * 16 + (lane & 15)];
-          const double b0 = Vs[row0 * VLD + tj * 16 + (lane & 15)];
-          w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, w0, 0, 0, 0);
-        }
+        if (ks < ks_hi) w0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, w0, 0, 0, 0);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           Ws[(ti * 16 + (lane >> 4) + 4 * r) * VLD + tj * 16 + (lane & 15)] = w0[r] + w1[r];
