@@ -624,6 +624,236 @@ q2_apply(Q2Args a) {
   }
 }
 
+// ---------------------------------------------------------------- b = 64: window in registers
+//
+// Each wave owns 16 columns of Z and keeps its 128-row window (8 tiles of 16 rows)
+// in registers as MFMA accumulator tiles: slot s holds window rows
+// 16 T + (lane >> 4) + 4 r (r = 0..3), column lane & 15, of the tile T with
+// T mod 8 == s.  That is the output layout of the update Z += V X, and also the
+// B-operand layout of W1 = V^T Z (k step 4u + r of a block is element r of its
+// tile u); the output of W1 is in turn the B operand of X = -T W1.  A block is
+// therefore three chained MFMA products with no data movement, and only V and T
+// go through LDS (double buffered: one barrier per block).  With b = 64 and
+// NBW = 32, block (jh, t) covers window tiles 4t + 2 .. 4t + 7 and block (jl, t)
+// tiles 4t .. 4t + 5, so the slots repeat every two positions and the position
+// loop is unrolled by two with every slot number fixed at compile time.  Zeros
+// known from the shapes are skipped: reflector c of a block is supported on rows
+// [c, c + 64), and T is upper triangular.
+constexpr int RCOLS = 64;  // columns per workgroup, 16 per wave
+
+struct Q2Pass {
+  int64_t jh, jl, base, nrel, Ph, Pl;
+  bool two;
+};
+
+__device__ inline Q2Pass q2_pass(const Q2Args& a, int64_t jh) {
+  Q2Pass p;
+  p.jh = jh;
+  p.two = jh >= 1;
+  p.jl = p.two ? jh - 1 : jh;
+  p.base = p.jl * NBW + 1;
+  p.nrel = a.n - p.base;
+  p.Pl = positions(a.n, a.b, p.jl * NBW);
+  p.Ph = p.two ? positions(a.n, a.b, jh * NBW) : 0;
+  return p;
+}
+
+// The block applied after (upper ? jh : jl, t): its group g and position tn;
+// false after the last block of the last pass.
+__device__ inline bool q2_next(const Q2Args& a, const Q2Pass& p, bool upper, int64_t t,
+                               int64_t& g, int64_t& tn) {
+  if (upper) {
+    g = p.jl;
+    tn = t;
+    return true;
+  }
+  if (t + 1 < p.Pl) {
+    g = (p.two && t + 1 < p.Ph) ? p.jh : p.jl;
+    tn = t + 1;
+    return true;
+  }
+  if (p.jh - 2 < 0) return false;
+  const Q2Pass q = q2_pass(a, p.jh - 2);
+  g = q.Ph > 0 ? q.jh : q.jl;
+  tn = 0;
+  return true;
+}
+
+struct VTStage {
+  double v[PV], t[PT];
+};
+
+__device__ inline void vt_fetch(const Q2Args& a, int64_t g, int64_t t, VTStage& f) {
+  const double* blk = a.V + (g * a.kmax + t) * (int64_t)(HP * NBW);
+  const double* Tg = a.T + (g * a.kmax + t) * NBW * NBW;
+#pragma unroll
+  for (int i = 0; i < PV; ++i) f.v[i] = blk[threadIdx.x + NT * i];
+#pragma unroll
+  for (int i = 0; i < PT; ++i) f.t[i] = Tg[threadIdx.x + NT * i];
+}
+
+__device__ inline void vt_commit(const VTStage& f, double* Vs, double* Tt) {
+#pragma unroll
+  for (int i = 0; i < PV; ++i) {
+    const int idx = threadIdx.x + NT * i;
+    Vs[(idx >> 5) * VLD + (idx & 31)] = f.v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = threadIdx.x + NT * i;
+    Tt[(idx >> 5) * VLD + (idx & 31)] = f.t[i];
+  }
+}
+
+struct ZCol {
+  double* z;      // this lane's column of Z (row 0 of the matrix)
+  bool ok;        // column inside Z
+  int64_t base;   // matrix row of window row 0
+  int64_t nrel;   // window rows inside the matrix
+};
+
+__device__ inline v4d z_load(const ZCol& zc, int64_t tile) {
+  const int l4 = (threadIdx.x & 63) >> 4;
+  v4d v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = 16 * tile + l4 + 4 * r;
+    v[r] = (zc.ok && row < zc.nrel) ? zc.z[zc.base + row] : 0.0;
+  }
+  return v;
+}
+
+__device__ inline void z_store(const ZCol& zc, int64_t tile, const v4d& v) {
+  const int l4 = (threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = 16 * tile + l4 + 4 * r;
+    if (zc.ok && row < zc.nrel) zc.z[zc.base + row] = v[r];
+  }
+}
+
+// One block on window slots S0 .. S0 + 5 (mod 8), V / T from LDS buffer cur; the
+// next block's V / T are fetched meanwhile and committed to the other buffer.
+template <int S0>
+__device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool upper, int64_t t,
+                                         v4d (&Z)[8], double (*Vs)[HP * VLD],
+                                         double (*Tt)[NBW * VLD], int& cur) {
+  const int lane = threadIdx.x & 63, l15 = lane & 15, l4 = lane >> 4;
+  int64_t gn = 0, tn = 0;
+  const bool more = q2_next(a, p, upper, t, gn, tn);
+  VTStage st;
+  if (more) vt_fetch(a, gn, tn, st);
+  const double* V = Vs[cur];
+  const double* Tb = Tt[cur];
+  // W (32 x 16) = V^T Z: c tile 0 meets window tiles 0..4, c tile 1 tiles 1..5
+  v4d W0 = {0.0, 0.0, 0.0, 0.0}, W1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double* vr = V + (16 * u + 4 * r + l4) * VLD + l15;
+      if (u <= 4) W0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], Z[(S0 + u) & 7][r], W0, 0, 0, 0);
+      if (u >= 1) W1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], Z[(S0 + u) & 7][r], W1, 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);  // bound the operands held in flight
+  }
+  W0 = -W0;
+  W1 = -W1;
+  // X = T (-W): T(c', c) = Tt[c][c'], zero for c' > c
+  v4d X0 = {0.0, 0.0, 0.0, 0.0}, X1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double* t0 = Tb + (4 * r + l4) * VLD + l15;
+    const double* t1 = Tb + (16 + 4 * r + l4) * VLD + l15;
+    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[0], W0[r], X0, 0, 0, 0);
+    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[0], W1[r], X0, 0, 0, 0);
+    X1 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[16], W1[r], X1, 0, 0, 0);
+  }
+  // the next block's V / T go to the other buffer now, freeing their registers
+  if (more) vt_commit(st, Vs[cur ^ 1], Tt[cur ^ 1]);
+  __builtin_amdgcn_sched_barrier(0);
+  // Z += V X: window tile u meets c tile 0 for u <= 4 and c tile 1 for u >= 1
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double* vr = V + (16 * u + l15) * VLD + 4 * r + l4;
+      if (u <= 4)
+        Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], X0[r], Z[(S0 + u) & 7], 0, 0, 0);
+      if (u >= 1)
+        Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], X1[r], Z[(S0 + u) & 7], 0, 0, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  __syncthreads();
+  cur ^= 1;
+}
+
+// Positions t of one pass with t mod 2 == P: tiles 4t .. 4t + 7 sit in slots
+// 4P .. 4P + 7 (mod 8).  Before the upper block, the four tiles it adds
+// (4t + 4 .. 4t + 7, prefetched into S) replace the tiles the previous lower
+// block finished; after the lower block, tiles 4t .. 4t + 3 are final.
+template <int P>
+__device__ __forceinline__ void q2_position(const Q2Args& a, const Q2Pass& p, const ZCol& zc,
+                                            int64_t t, v4d (&Z)[8], v4d (&S)[4],
+                                            double (*Vs)[HP * VLD], double (*Tt)[NBW * VLD],
+                                            int& cur) {
+  constexpr int SL = (4 * P) & 7, SU = (4 * P + 2) & 7, SN = (4 * P + 4) & 7;
+  if (t >= 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Z[(SN + i) & 7] = S[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S[i] = z_load(zc, 4 * t + 8 + i);
+  }
+  if (p.two && t < p.Ph) q2_block<SU>(a, p, true, t, Z, Vs, Tt, cur);
+  q2_block<SL>(a, p, false, t, Z, Vs, Tt, cur);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) z_store(zc, 4 * t + i, Z[(SL + i) & 7]);
+}
+
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+q2_apply_reg(Q2Args a) {
+  __shared__ double Vs[2][HP * VLD];
+  __shared__ double Tt[2][NBW * VLD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t col = (int64_t)blockIdx.x * RCOLS + wave * 16 + (lane & 15);
+  ZCol zc;
+  zc.ok = col < a.ncols;
+  zc.z = a.Z + (zc.ok ? col : 0) * a.ldz;
+  if (a.ngroups <= 0) return;
+  int cur = 0;
+  {
+    const Q2Pass p = q2_pass(a, a.ngroups - 1);
+    VTStage st;
+    vt_fetch(a, p.Ph > 0 ? p.jh : p.jl, 0, st);
+    vt_commit(st, Vs[0], Tt[0]);
+  }
+  __syncthreads();
+  v4d Z[8], S[4];
+  for (int64_t jh = a.ngroups - 1; jh >= 0; jh -= 2) {
+    const Q2Pass p = q2_pass(a, jh);
+    zc.base = p.base;
+    zc.nrel = p.nrel;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) Z[s] = z_load(zc, s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S[i] = z_load(zc, 8 + i);
+    for (int64_t t = 0; t < p.Pl; t += 2) {
+      q2_position<0>(a, p, zc, t, Z, S, Vs, Tt, cur);
+      if (t + 1 < p.Pl) q2_position<1>(a, p, zc, t + 1, Z, S, Vs, Tt, cur);
+    }
+    // the four tiles loaded last, 4 Pl .. 4 Pl + 3
+    if ((p.Pl & 1) == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z_store(zc, 4 * p.Pl + i, Z[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z_store(zc, 4 * p.Pl + i, Z[4 + i]);
+    }
+  }
+}
+
 }  // namespace
 
 size_t apply_q2_workspace(int64_t n, int b) {
@@ -647,7 +877,10 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
   {
     // algorithmic flops: ~n^2 / (2b) reflectors of length b, 4b flops per column each
     ProbeScope probe(PROBE_Q2_APPLY, s, 2.0 * (double)n * (double)n * (double)ncols);
-    hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
+    if (c.b == 64)
+      hipLaunchKernelGGL(q2_apply_reg, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
+    else
+      hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
     GEP_LAUNCH_CHECK();
   }
 }

@@ -44,6 +44,29 @@ def test_solve_small(gpu, M):
     check_against_oracle(A, B, to_np(lam), to_np(Y))
 
 
+@pytest.mark.parametrize("M", [2113, 3001])
+def test_solve_band64_ragged(gpu, M):
+    """Orders >= 2048 reduce to band width 64, whose Q2 back transformation keeps
+    each wave's window of Z in registers; ragged orders leave a partial column
+    strip and partial row tiles.  The oracle's eigensolver is too slow here, so:
+    residual and B-orthogonality (together they make (lam, Y) a complete
+    eigendecomposition up to rounding) and the oracle's exact counts of
+    eigenvalues below fixed shifts (Sylvester's law of inertia on A - sigma B)."""
+    say(f"[solve] band 64, M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 500 + M)
+    lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    n1 = np.abs(A).sum(axis=0).max()
+    assert np.all(np.diff(lam) >= 0)
+    orth = np.abs(Y.T @ B @ Y - np.eye(M)).max()
+    assert orth <= TOL_ORTH, orth
+    res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+    assert res <= TOL_RES, res
+    for sigma in (-3.3, -0.7, 1.9):  # fixed before any solve
+        assert np.abs(lam - sigma).min() > 1e-9 * n1  # no eigenvalue at the shift
+        assert int(np.count_nonzero(lam < sigma)) == oracle.inertia_count(A, B, sigma), sigma
+
+
 def test_solve_c1_workload(gpu):
     """The 512 workload (decay length 8, seed 1)."""
     say("[solve] m512 workload")
