@@ -755,7 +755,6 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
       if (u <= 4) W0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], Z[(S0 + u) & 7][r], W0, 0, 0, 0);
       if (u >= 1) W1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], Z[(S0 + u) & 7][r], W1, 0, 0, 0);
     }
-    __builtin_amdgcn_sched_barrier(0);  // bound the operands held in flight
   }
   W0 = -W0;
   W1 = -W1;
@@ -769,9 +768,7 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
     X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[0], W1[r], X0, 0, 0, 0);
     X1 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[16], W1[r], X1, 0, 0, 0);
   }
-  // the next block's V / T go to the other buffer now, freeing their registers
-  if (more) vt_commit(st, Vs[cur ^ 1], Tt[cur ^ 1]);
-  __builtin_amdgcn_sched_barrier(0);
+
   // Z += V X: window tile u meets c tile 0 for u <= 4 and c tile 1 for u >= 1
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
@@ -783,8 +780,8 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
       if (u >= 1)
         Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], X1[r], Z[(S0 + u) & 7], 0, 0, 0);
     }
-    __builtin_amdgcn_sched_barrier(0);
   }
+  if (more) vt_commit(st, Vs[cur ^ 1], Tt[cur ^ 1]);
   __syncthreads();
   cur ^= 1;
 }
