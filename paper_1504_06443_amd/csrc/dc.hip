@@ -657,6 +657,54 @@ Work carve(Arena& ws, int64_t n) {
 
 }  // namespace
 
+namespace {
+
+constexpr int64_t HOST_SIZED_MIN = 8192;
+constexpr unsigned HOST_SIZED_MAX_P = 4;  // merges per level (top three levels)
+
+bool fast_aligned(const GemmDesc& d) {
+  return (uintptr_t)d.A % 16 == 0 && (uintptr_t)d.B % 16 == 0 && d.lda % 2 == 0 && d.ldb % 2 == 0;
+}
+
+// Run a level's merge GEMMs (descriptor pairs top, bottom per merge, written by
+// merge_gather) with sizes read back to the host.  The bottom product starts at
+// column K1 of G (K1: the top half's undeflated count, the row offset of its B
+// operand in U relative to the top product's); an odd K1 leaves that operand off
+// the 16-byte alignment of the fast path.  G's column K1 - 1 is then a top-half
+// eigenvector, exactly zero in the bottom half's rows, so starting one column
+// earlier adds an exact zero term.  A product still misaligned (an odd node start
+// in a ragged order) runs as a grouped launch of its own descriptor.
+void merge_gemms_host(const GemmDesc* desc, int count, hipStream_t s) {
+  GemmDesc hd[2 * HOST_SIZED_MAX_P];
+  GEP_HIP(hipMemcpyAsync(hd, desc, (size_t)count * sizeof(GemmDesc), hipMemcpyDeviceToHost, s));
+  GEP_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) {
+    GemmDesc d = hd[i];
+    if (d.m <= 0 || d.n <= 0) continue;
+    if ((i & 1) && (uintptr_t)d.B % 16 != 0) {
+      const int64_t K1 = d.B - hd[i - 1].B;
+      if (K1 >= 1) {
+        d.A -= d.lda;
+        d.B -= 1;
+        d.k += 1;
+      }
+    }
+    if (!fast_aligned(d)) {
+      gemm_grouped(desc + i, 1, d.m, d.n, s);
+      continue;
+    }
+    Gemm g;
+    g.transA = d.transA != 0;
+    g.transB = d.transB != 0;
+    g.m = d.m; g.n = d.n; g.k = d.k;
+    g.alpha = d.alpha; g.beta = d.beta;
+    g.A = d.A; g.lda = d.lda; g.B = d.B; g.ldb = d.ldb; g.C = d.C; g.ldc = d.ldc;
+    gemm(g, s);
+  }
+}
+
+}  // namespace
+
 size_t stedc_workspace(int64_t n) {
   Arena a;
   a.dry = true;
@@ -669,6 +717,19 @@ void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, 
   if (n <= 0) return;
   Work w = carve(ws, n);
   const int D = tree_depth(n);
+  // The top merges' GEMMs dominate large orders.  Their sizes depend on deflation
+  // and live on the device; for an order >= HOST_SIZED_MIN on a stream that is not
+  // being captured, the few descriptors of each of the top levels are read back
+  // (one small copy and stream sync per level) and run on the tiled GEMM path with
+  // host-side sizes, whose 128 x 128 interior kernel is faster than the grouped
+  // one.  Graph capture allows no sync, and small orders (batched solves) keep the
+  // launching thread free, so both use the grouped launch.
+  bool host_sized = false;
+  if (n >= HOST_SIZED_MIN) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GEP_HIP(hipStreamIsCapturing(s, &cs));
+    host_sized = cs == hipStreamCaptureStatusNone;
+  }
   set_matrix(n, n, 0.0, 0.0, Z, ldz, s);
   hipLaunchKernelGGL(leaf_kernel, dim3((unsigned)((int64_t)1 << D)), dim3(64), 0, s, n, D, d, e, lam,
                      Z, ldz, info);
@@ -693,7 +754,10 @@ void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, 
     hipLaunchKernelGGL(merge_gather, dim3((unsigned)Nmax, P), dim3(256), 0, s, n, t, w,
                        (const double*)Z, ldz);
     GEP_LAUNCH_CHECK();
-    gemm_grouped(w.desc, (int)(2 * P), Nmax, Nmax, s);
+    if (host_sized && P <= HOST_SIZED_MAX_P)
+      merge_gemms_host(w.desc, (int)(2 * P), s);
+    else
+      gemm_grouped(w.desc, (int)(2 * P), Nmax, Nmax, s);
     hipLaunchKernelGGL(merge_scatter, dim3((unsigned)Nmax, P), dim3(256), 0, s, n, t, w, lam, Z, ldz);
     GEP_LAUNCH_CHECK();
   }

@@ -108,6 +108,28 @@ def _tridiag_cases():
     return cases
 
 
+@pytest.mark.parametrize("M", [8192, 8195])
+def test_tridiag_eig_large_matches_oracle(gpu, M):
+    """Orders >= 8192 run the top three merge levels' GEMMs with host-side sizes
+    on the tiled GEMM path.  An even order takes the fast kernel (with the bottom
+    product shifted by one zero column when the top half's undeflated count is
+    odd); an odd order (odd leading dimension) takes the grouped fallback."""
+    say(f"[stedc] large random M={M}")
+    rng = np.random.default_rng(11 + M)
+    d, e = rng.standard_normal(M), rng.standard_normal(M - 1)
+    lam, Z = _gep().tridiag_eig(to_gpu(d), to_gpu(e))
+    lam, Z = to_np(lam), to_np(Z)
+    w_ref = oracle.tridiag_eigvals(d, e)
+    tn = np.abs(d).max() + 2 * np.abs(e).max()
+    assert np.all(np.diff(lam) >= 0)
+    assert np.abs(lam - w_ref).max() <= 1e-13 * tn * 4
+    assert np.abs(Z.T @ Z - np.eye(M)).max() <= 1e-13 * np.sqrt(M)
+    TZ = d[:, None] * Z
+    TZ[1:] += e[:, None] * Z[:-1]
+    TZ[:-1] += e[:, None] * Z[1:]
+    assert np.abs(TZ - Z * lam[None, :]).max() <= 1e-13 * tn * np.sqrt(M)
+
+
 @pytest.mark.parametrize("name,d,e", _tridiag_cases(), ids=lambda x: x if isinstance(x, str) else "")
 def test_tridiag_eig_matches_oracle(gpu, name, d, e):
     say(f"[stedc] {name} M={d.size}")
