@@ -20,53 +20,84 @@ constexpr int LDS_LD = NB + 1;
 // slot, zeros above the diagonal) to linv.  A non-positive pivot at local column
 // j records info = info_add + row0 + j + 1 (first failure wins) and the pivot is
 // replaced by 1 so that later steps stay finite.
+//
+// Right-looking: step j scales column j of L and updates the trailing lower
+// triangle.  The inverse X = L^{-1} is built in the same steps by applying each
+// step's elimination to the identity (row j of X divided by L(j,j), then
+// X(i, 0:j) -= L(i,j) X(j, 0:j) for i > j), which is as parallel as the trailing
+// update; the strictly lower part of X is kept transposed in the unused upper
+// triangle of the LDS block (X(i,c) at row c, column i) and its diagonal in xd.
 __global__ void __launch_bounds__(NT)
 potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict__ linv,
                  int32_t* __restrict__ info, int64_t row0, int64_t info_add) {
   extern __shared__ double S[];  // column-major, ld LDS_LD
-  double* tcol = S + (size_t)NB * LDS_LD;
+  double* xd = S + (size_t)NB * LDS_LD;
   const int tid = threadIdx.x;
   for (int j = tid >> 7; j < n; j += NT / 128)
     for (int i = tid & 127; i < n; i += 128) S[i + j * LDS_LD] = (i >= j) ? a[i + j * lda] : 0.0;
   __syncthreads();
-  // right-looking factorisation
   for (int j = 0; j < n; ++j) {
     const double piv = S[j + j * LDS_LD];
     const bool ok = piv > 0.0;  // false for NaN too
     const double ljj = ok ? sqrt(piv) : 1.0;
     if (!ok && tid == 0 && info) atomicCAS(info, 0, (int32_t)(info_add + row0 + j + 1));
     __syncthreads();
-    if (tid == 0) S[j + j * LDS_LD] = ljj;
     const double rl = 1.0 / ljj;
-    for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LDS_LD] *= rl;
+    if (tid == 0) {
+      S[j + j * LDS_LD] = ljj;
+      xd[j] = rl;
+    }
+    for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LDS_LD] *= rl;  // L(j+1:, j)
+    for (int c = tid; c < j; c += NT) S[c + j * LDS_LD] *= rl;          // X(j, 0:j)
     __syncthreads();
-    // trailing update of the lower triangle: 2 threads per column
+    // trailing update of L's lower triangle: 2 threads per column, eight rows'
+    // operands read before any of their updates is written (one LDS round trip
+    // per eight elements instead of one per element)
     for (int k = j + 1 + (tid >> 1); k < n; k += NT / 2) {
       const double lkj = S[k + j * LDS_LD];
-      for (int i = k + (tid & 1); i < n; i += 2) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * lkj;
+      int i = k + (tid & 1);
+      for (; i + 14 < n; i += 16) {
+        double lj[8], sk[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          lj[u] = S[i + 2 * u + j * LDS_LD];
+          sk[u] = S[i + 2 * u + k * LDS_LD];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) S[i + 2 * u + k * LDS_LD] = sk[u] - lj[u] * lkj;
+      }
+      for (; i < n; i += 2) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * lkj;
+    }
+    // X(i, 0:j+1) -= L(i,j) X(j, 0:j+1) for i > j: 2 threads per row, batched the
+    // same way
+    for (int i = j + 1 + (tid >> 1); i < n; i += NT / 2) {
+      const double lij = S[i + j * LDS_LD];
+      int c = tid & 1;
+      for (; c + 14 < j; c += 16) {
+        double xj[8], xi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          xj[u] = S[c + 2 * u + j * LDS_LD];
+          xi[u] = S[c + 2 * u + i * LDS_LD];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) S[c + 2 * u + i * LDS_LD] = xi[u] - lij * xj[u];
+      }
+      for (; c <= j; c += 2) {
+        const double xjc = (c == j) ? rl : S[c + j * LDS_LD];
+        S[c + i * LDS_LD] -= lij * xjc;
+      }
     }
     __syncthreads();
   }
   for (int j = tid >> 7; j < n; j += NT / 128)
     for (int i = tid & 127; i < n; i += 128) a[i + j * lda] = (i >= j) ? S[i + j * LDS_LD] : 0.0;
-  // in-place inverse, columns right to left:
-  //   X(j,j) = 1/L(j,j);  X(j+1:, j) = -X(j+1:, j+1:) L(j+1:, j) X(j,j)
-  for (int j = n - 1; j >= 0; --j) {
-    __syncthreads();
-    for (int i = tid; i < n; i += NT) tcol[i] = S[i + j * LDS_LD];
-    __syncthreads();
-    const double xjj = 1.0 / tcol[j];
-    for (int i = j + 1 + tid; i < n; i += NT) {
-      double s = 0.0;
-      for (int k = j + 1; k <= i; ++k) s += S[i + k * LDS_LD] * tcol[k];
-      S[i + j * LDS_LD] = -s * xjj;
-    }
-    if (tid == 0) S[j + j * LDS_LD] = xjj;
-  }
-  __syncthreads();
   for (int j = tid >> 7; j < NB; j += NT / 128)
-    for (int i = tid & 127; i < NB; i += 128)
-      linv[i + j * NB] = (i < n && j < n && i >= j) ? S[i + j * LDS_LD] : 0.0;
+    for (int i = tid & 127; i < NB; i += 128) {
+      double x = 0.0;
+      if (i < n && j < n && i >= j) x = (i == j) ? xd[j] : S[j + i * LDS_LD];
+      linv[i + j * NB] = x;
+    }
 }
 
 int64_t split_point(int64_t n) {
