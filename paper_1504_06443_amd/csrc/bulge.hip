@@ -205,25 +205,46 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
       const int L = (int)((n - r) < b ? (n - r) : b);  // reflector length
       const int64_t c = r - b;                   // first column of the block left of D
       // load D (rows/cols r.., symmetric from the lower band) and the column
-      // block to its left (column s for k = 0, the bulge block E otherwise)
+      // block to its left (column s for k = 0, the bulge block E otherwise).
+      // Each thread issues all its coherent loads back to back (addresses of
+      // unused slots clamped to a valid element) and only then writes LDS, so
+      // the loads' latencies overlap instead of adding up.
       {
-        const int i = tid & 63;
-        if (i < L)
-          for (int j = tid >> 6; j <= i; j += NT / 64) {
-            const double x = cld(&band[(i - j) + (r + j) * ld]);
-            Ds[i + j * LDS_LD] = x;
-            Ds[j + i * LDS_LD] = x;
-          }
-      }
-      if (k == 0) {
-        if (tid < L) v[tid] = cld(&band[(1 + tid) + s * ld]);
-      } else {
-        {
-          const int i = tid & 63;
-          if (i < L)
-            for (int j = tid >> 6; j < Lprev; j += NT / 64)
-              Es[i + j * LDS_LD] = cld(&band[(b + i - j) + (c + j) * ld]);
+        const int i = tid & 63, j0 = tid >> 6;
+        constexpr int PER = MAXB / (NT / 64);  // 16 elements per thread and block
+        double xd[PER], xe[PER];
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+          const int j = j0 + (NT / 64) * m;
+          const bool okd = i < L && j <= i;
+          xd[m] = cld(&band[okd ? (i - j) + (r + j) * ld : 0]);
         }
+        if (k > 0) {
+#pragma unroll
+          for (int m = 0; m < PER; ++m) {
+            const int j = j0 + (NT / 64) * m;
+            const bool oke = i < L && j < Lprev;
+            xe[m] = cld(&band[oke ? (b + i - j) + (c + j) * ld : 0]);
+          }
+        }
+        double xv = 0.0;
+        if (k == 0 && tid < L) xv = cld(&band[(1 + tid) + s * ld]);
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+          const int j = j0 + (NT / 64) * m;
+          if (i < L && j <= i) {
+            Ds[i + j * LDS_LD] = xd[m];
+            Ds[j + i * LDS_LD] = xd[m];
+          }
+        }
+        if (k > 0) {
+#pragma unroll
+          for (int m = 0; m < PER; ++m) {
+            const int j = j0 + (NT / 64) * m;
+            if (i < L && j < Lprev) Es[i + j * LDS_LD] = xe[m];
+          }
+        }
+        if (k == 0 && tid < L) v[tid] = xv;
       }
       __syncthreads();
       double beta, tau;
