@@ -179,7 +179,20 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
         v = Ps[i * LDP + c] * scal;
         Ps[i * LDP + c] = v;
       }
-      for (int j = c + 1; j < w; ++j) Ps[i * LDP + j] -= v * wv[j];
+      // eight columns' operands read before their updates are written (one LDS
+      // round trip per eight elements)
+      int j = c + 1;
+      for (; j + 7 < w; j += 8) {
+        double x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          x[u] = Ps[i * LDP + j + u];
+          y[u] = wv[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) Ps[i * LDP + j + u] = x[u] - v * y[u];
+      }
+      for (; j < w; ++j) Ps[i * LDP + j] -= v * wv[j];
     }
     if (g == 0 && tid == 0) a.tau[c] = tau;
     __syncthreads();
