@@ -88,21 +88,26 @@ def kernel_traffic(kernel: str, workload: str):
 
 def batched_extension(gep, torch, replays: int = 5) -> dict:
     """The 256-instance batch (orders log-uniform in [64, 2048], instance seeds
-    4000+i), FP64 with vectors, one gep_solve_batched call captured in a HIP graph;
-    replay time (median) -> solves/s and algorithmic TFLOP/s."""
+    4000+i), FP64 with vectors.  Eager: one gep_solve_batched call.  Replay: the
+    batch split largest-first into 16 groups, each group's call captured in its
+    own graph on its own stream, all graphs replayed concurrently (BatchedGraph);
+    replay time (median) -> solves/s and algorithmic TFLOP/s.  The replayed
+    results must equal the eager call's bit for bit."""
     import synth
     sizes = synth.batch_sizes()
     bs = gep.BatchedSolver(sizes)
+    bg = gep.BatchedGraph(sizes, groups=16)
     As, Bs = [], []
     for i, M in enumerate(sizes):
         A, B = synth.batch_instance(i, M)
-        As.append(torch.from_numpy(A))
-        Bs.append(torch.from_numpy(B))
-    bs.load([a.cuda() for a in As], [b.cuda() for b in Bs])
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+    bs.load(As, Bs)
+    bg.load(As, Bs)
     del As, Bs
     bs.run()
     torch.cuda.synchronize()
-    ref = [l.clone() for l, _ in bs.results()]
+    ref = [(l.clone(), Y.clone()) for l, Y in bs.results()]
     eager = []
     for _ in range(3):
         torch.cuda.synchronize()
@@ -111,32 +116,26 @@ def batched_extension(gep, torch, replays: int = 5) -> dict:
         torch.cuda.synchronize()
         eager.append(time.perf_counter() - t0)
     Te = sorted(eager)[1]
-    s = torch.cuda.Stream()
-    s.wait_stream(torch.cuda.current_stream())
-    g = torch.cuda.CUDAGraph()
-    with torch.cuda.stream(s):
-        bs.run()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        with torch.cuda.graph(g, stream=s):
-            bs.run()
-        t_capture = time.perf_counter() - t0
-    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bg.capture()
+    t_capture = time.perf_counter() - t0
     times = []
     for _ in range(replays):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        g.replay()
+        bg.replay()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-    same = all(torch.equal(l, l0) for (l, _), l0 in zip(bs.results(), ref))
+    same = all(torch.equal(l, l0) and torch.equal(Y, Y0)
+               for (l, Y), (l0, Y0) in zip(bg.results(), ref))
     T = sorted(times)[len(times) // 2]
     flops = sum(alg_flops(M) for M in sizes)
     print(f"[bench] batched: eager {Te * 1e3:.1f} ms, graph replay {T * 1e3:.1f} ms "
-          f"({len(sizes)} solves)", file=sys.stderr, flush=True)
+          f"({len(sizes)} solves, {len(bg.members)} per-stream graphs)", file=sys.stderr, flush=True)
     return {"workload": "batch256_logu64_2048_seed4", "instances": len(sizes),
             "replay_ms_median": T * 1e3, "solves_per_s": len(sizes) / T,
             "tflops_fp64": flops / T / 1e12, "capture_ms": t_capture * 1e3,
+            "graphs": len(bg.members),
             "eager_ms_median": Te * 1e3, "eager_solves_per_s": len(sizes) / Te,
             "replays_equal_eager": bool(same)}
 

@@ -236,6 +236,83 @@ class BatchedSolver:
         return list(zip(self.lam, Ys))
 
 
+class BatchedGraph:
+    """A fixed batch solved by graph replay.  The instances are split largest-first
+    (each to the group with the least sum of M^3) into `groups` sub-batches; each
+    sub-batch is one BatchedSolver whose gep_solve_batched call is captured in its
+    own graph on its own stream, and replay() launches all graphs concurrently.
+    (The HIP runtime here replays the parallel branches of a single captured graph
+    one node after another, so one graph of the whole batch replays about 2.4x
+    slower than the eager call; per-group graphs on separate streams keep the
+    groups concurrent.)  Results are identical to one BatchedSolver of the whole
+    batch: every instance runs the same kernels either way.
+    """
+
+    def __init__(self, sizes, groups=16, job="vectors", device="cuda:0"):
+        self.sizes = [int(m) for m in sizes]
+        groups = max(1, min(int(groups), len(self.sizes)))
+        order = sorted(range(len(self.sizes)), key=lambda i: -self.sizes[i])
+        self.members = [[] for _ in range(groups)]
+        load = [0] * groups
+        for i in order:
+            g = min(range(groups), key=lambda k: load[k])
+            self.members[g].append(i)
+            load[g] += self.sizes[i] ** 3
+        self.members = [m for m in self.members if m]
+        self.solvers = [BatchedSolver([self.sizes[i] for i in m], job=job, device=device)
+                        for m in self.members]
+        self.streams = [torch.cuda.Stream(device=device) for _ in self.members]
+        self.graphs = None
+
+    def load(self, As, Bs):
+        for m, sv in zip(self.members, self.solvers):
+            sv.load([As[i] for i in m], [Bs[i] for i in m])
+
+    def _each(self, fn):
+        cur = torch.cuda.current_stream()
+        for st, item in zip(self.streams, fn):
+            st.wait_stream(cur)
+            with torch.cuda.stream(st):
+                item()
+        for st in self.streams:
+            cur.wait_stream(st)
+
+    def run(self):
+        """Eager: every group's call on its own stream."""
+        self._each([sv.run for sv in self.solvers])
+
+    def capture(self):
+        self.run()
+        torch.cuda.synchronize()
+        self.graphs = []
+        for st, sv in zip(self.streams, self.solvers):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(st):
+                with torch.cuda.graph(g, stream=st):
+                    sv.run()
+            self.graphs.append(g)
+        torch.cuda.synchronize()
+
+    def replay(self):
+        if self.graphs is None:
+            raise RuntimeError("BatchedGraph.replay() before capture()")
+        self._each([g.replay for g in self.graphs])
+
+    @property
+    def info(self):
+        out = torch.empty(len(self.sizes), dtype=torch.int32, device=self.solvers[0].info.device)
+        for m, sv in zip(self.members, self.solvers):
+            out[torch.tensor(m, device=out.device)] = sv.info
+        return out
+
+    def results(self):
+        out = [None] * len(self.sizes)
+        for m, sv in zip(self.members, self.solvers):
+            for i, r in zip(m, sv.results()):
+                out[i] = r
+        return out
+
+
 def solve_batched(As, Bs, job="vectors", check_info=True):
     """Solve A_i y = lambda B_i y for lists of square float64 CUDA tensors of
     possibly different orders.  Returns a list of (lam, Y)."""

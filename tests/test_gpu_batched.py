@@ -100,3 +100,37 @@ def test_batch_graph_replay(gpu):
         torch.cuda.synchronize()
         for (l, Y), (l0, Y0) in zip(bs.results(), ref):
             assert torch.equal(l, l0) and torch.equal(Y, Y0), rep
+
+
+def test_batched_graph_per_stream_replay(gpu):
+    """BatchedGraph: the batch split into groups, one captured graph per group and
+    stream, replayed concurrently; every replay (with eager work and
+    synchronisations in between) must equal one eager call of the whole batch,
+    and the instance order of results() must be the caller's."""
+    import torch
+    gep = _gep()
+    sizes = [64, 65, 100, 129, 257, 300, 511, 700, 1024, 77, 64, 333, 2048, 190]
+    As, Bs = [], []
+    for i, M in enumerate(sizes):
+        A, B = synth.batch_instance(200 + i, M)
+        As.append(to_gpu(A))
+        Bs.append(to_gpu(B))
+    bs = gep.BatchedSolver(sizes)
+    bs.load(As, Bs)
+    bs.run()
+    torch.cuda.synchronize()
+    ref = [(l.clone(), Y.clone()) for l, Y in bs.results()]
+    bg = gep.BatchedGraph(sizes, groups=5)
+    assert sorted(i for m in bg.members for i in m) == list(range(len(sizes)))
+    bg.load(As, Bs)
+    bg.capture()
+    for rep in range(3):
+        for l, Y in bg.results():
+            l.zero_()
+            Y.zero_()
+        _ = torch.randn(1000, 1000, device="cuda").sum().item()  # eager work between replays
+        bg.replay()
+        torch.cuda.synchronize()
+        assert int(bg.info.abs().sum().item()) == 0
+        for (l, Y), (l0, Y0) in zip(bg.results(), ref):
+            assert torch.equal(l, l0) and torch.equal(Y, Y0), rep
