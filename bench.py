@@ -20,6 +20,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# Hardware queues per process (read when HIP initialises, i.e. before torch is
+# imported).  HIP's default of 4 folds the 16 worker streams of a batched solve
+# onto 4 queues; 32 lets them run concurrently.  Set here rather than inherited:
+# the default may also arrive through the environment.  Single solves use one
+# stream and are unaffected.
+os.environ["GPU_MAX_HW_QUEUES"] = "32"
+
 METRIC = "GEP solves/s + FP64 TFLOP/s at M=32768; mixed-vs-FP64 speedup at 1e-11 err"
 PEAK_FP64 = 78.6  # TFLOP/s, MI355X dense FP64 (matrix == vector)
 PHASE_FLOPS = {

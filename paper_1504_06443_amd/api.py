@@ -245,7 +245,10 @@ class BatchedGraph:
     one node after another, so one graph of the whole batch replays about 2.4x
     slower than the eager call; per-group graphs on separate streams keep the
     groups concurrent.)  Results are identical to one BatchedSolver of the whole
-    batch: every instance runs the same kernels either way.
+    batch: every instance runs the same kernels either way.  Concurrency between
+    streams needs enough hardware queues in the process: HIP's default
+    GPU_MAX_HW_QUEUES of 4 folds the streams onto 4 queues (set it, e.g. to 32,
+    before HIP initialises).
     """
 
     def __init__(self, sizes, groups=16, job="vectors", device="cuda:0"):
