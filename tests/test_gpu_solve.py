@@ -44,11 +44,12 @@ def test_solve_small(gpu, M):
     check_against_oracle(A, B, to_np(lam), to_np(Y))
 
 
-@pytest.mark.parametrize("M", [2113, 3001])
+@pytest.mark.parametrize("M", [2080, 2113, 3001])
 def test_solve_band64_ragged(gpu, M):
     """Orders >= 2048 reduce to band width 64, whose Q2 back transformation keeps
     each wave's window of Z in registers; ragged orders leave a partial column
-    strip and partial row tiles.  The oracle's eigensolver is too slow here, so:
+    strip and partial row tiles.  M = 2080 has an odd number of 32-sweep groups
+    (65), so its last pass over Z applies one group alone.  The oracle's eigensolver is too slow here, so:
     residual and B-orthogonality (together they make (lam, Y) a complete
     eigendecomposition up to rounding) and the oracle's exact counts of
     eigenvalues below fixed shifts (Sylvester's law of inertia on A - sigma B)."""
