@@ -375,12 +375,24 @@ __global__ void merge_rotate(int64_t n, int t, Work w, double* __restrict__ Z, i
 
 // w(x) = 1/rho + sum_l z_l^2 / (D_l - x) in coordinates relative to the origin pole.
 // (d) secular equation, one thread per root.
+// Sum over the aligned group of SEC_LANES lanes that share one root.
+constexpr int SEC_LANES = 8;
+__device__ inline double group_sum(double v) {
+#pragma unroll
+  for (int off = 1; off < SEC_LANES; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// One root per group of SEC_LANES lanes: the lanes split the pole sums (terms
+// l = sub, sub + SEC_LANES, ...) and every lane gets the group's totals, so all
+// lanes of a group take the same steps and the same convergence decision.
 __global__ void merge_secular(int64_t n, int t, Work w, int32_t* info) {
   const Node nd = merge_node(n, t, blockIdx.y);
   const MergeInfo mi = w.info[blockIdx.y];
   const int K = mi.K;
-  const int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= K) return;
+  const int sub = threadIdx.x & (SEC_LANES - 1);
+  const int q = blockIdx.x * (blockDim.x / SEC_LANES) + threadIdx.x / SEC_LANES;
+  if (q >= K) return;  // whole groups leave together
   const double* d = w.sd + nd.lo;
   const double* z = w.sz + nd.lo;
   const double rho = mi.rho;
@@ -389,15 +401,17 @@ __global__ void merge_secular(int64_t n, int t, Work w, int32_t* info) {
   double lo, hi;
   if (q == K - 1) {
     double zs = 0.0;
-    for (int l = 0; l < K; ++l) zs += z[l] * z[l];
+    for (int l = sub; l < K; l += SEC_LANES) zs += z[l] * z[l];
+    zs = group_sum(zs);
     o = q;
     lo = 0.0;
     hi = rho * zs;
   } else {
     const double gap = d[q + 1] - d[q];
     const double mid = 0.5 * gap;
-    double wv = rrho;
-    for (int l = 0; l < K; ++l) wv += z[l] * z[l] / ((d[l] - d[q]) - mid);
+    double wp = 0.0;
+    for (int l = sub; l < K; l += SEC_LANES) wp += z[l] * z[l] / ((d[l] - d[q]) - mid);
+    const double wv = rrho + group_sum(wp);
     if (wv >= 0.0) {
       o = q; lo = 0.0; hi = mid;
     } else {
@@ -409,12 +423,16 @@ __global__ void merge_secular(int64_t n, int t, Work w, int32_t* info) {
   bool conv = false;
   for (int it = 0; it < 200; ++it) {
     double psi = 0.0, dpsi = 0.0, phi = 0.0, dphi = 0.0;
-    for (int l = 0; l < K; ++l) {
+    for (int l = sub; l < K; l += SEC_LANES) {
       const double del = (d[l] - dorg) - tau;
       const double r = z[l] / del;
       if (l <= q) { psi += z[l] * r; dpsi += r * r; }
       else { phi += z[l] * r; dphi += r * r; }
     }
+    psi = group_sum(psi);
+    dpsi = group_sum(dpsi);
+    phi = group_sum(phi);
+    dphi = group_sum(dphi);
     const double wv = rrho + psi + phi;
     const double err = 8.0 * (rrho + fabs(psi) + fabs(phi)) + fabs(tau) * (dpsi + dphi);
     if (fabs(wv) <= EPS * err) { conv = true; break; }
@@ -452,6 +470,7 @@ __global__ void merge_secular(int64_t n, int t, Work w, int32_t* info) {
     if (!(nt > lo && nt < hi)) nt = 0.5 * (lo + hi);
     tau = nt;
   }
+  if (sub != 0) return;
   if (!conv && info) atomicCAS(info, 0, (int32_t)(nd.lo + q + 1));
   w.orig[nd.lo + q] = o;
   w.tau[nd.lo + q] = tau;
@@ -745,7 +764,8 @@ void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, 
     hipLaunchKernelGGL(merge_rotate, dim3((unsigned)cdiv(Nmax, 256), P), dim3(256), 0, s, n, t, w, Z,
                        ldz);
     GEP_LAUNCH_CHECK();
-    hipLaunchKernelGGL(merge_secular, dim3((unsigned)cdiv(Nmax, 64), P), dim3(64), 0, s, n, t, w, info);
+    hipLaunchKernelGGL(merge_secular, dim3((unsigned)cdiv(Nmax, 64 / SEC_LANES), P), dim3(64), 0, s,
+                       n, t, w, info);
     GEP_LAUNCH_CHECK();
     hipLaunchKernelGGL(merge_zhat, dim3((unsigned)cdiv(Nmax, 64), P), dim3(64), 0, s, n, t, w);
     GEP_LAUNCH_CHECK();
