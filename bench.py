@@ -135,6 +135,22 @@ def batched_extension(gep, torch, replays: int = 5) -> dict:
         times.append(time.perf_counter() - t0)
     same = all(torch.equal(l, l0) and torch.equal(Y, Y0)
                for (l, Y), (l0, Y0) in zip(bg.results(), ref))
+    # worst per-instance residual ||AY - BY diag(lam)||_1 / (||A||_1 ||Y||_1) and
+    # max|Y^T B Y - I|, with torch FP64 products on the solver's own copies of A, B
+    worst_res = worst_orth = 0.0
+    for A, B, (lam, Y) in zip(bs.A, bs.B, bg.results()):
+        Al = torch.tril(A)
+        Af = Al + Al.t() - torch.diag(torch.diagonal(A))
+        Bl = torch.tril(B)
+        Bf = Bl + Bl.t() - torch.diag(torch.diagonal(B))
+        Yc = Y.contiguous()
+        BY = Bf @ Yc
+        R = Af @ Yc - BY * lam[None, :]
+        n1 = Af.abs().sum(0).max()
+        worst_res = max(worst_res, (R.abs().sum(0).max() / (n1 * Yc.abs().sum(0).max())).item())
+        G = Yc.t() @ BY
+        G.diagonal().sub_(1.0)
+        worst_orth = max(worst_orth, G.abs().max().item())
     T = sorted(times)[len(times) // 2]
     flops = sum(alg_flops(M) for M in sizes)
     print(f"[bench] batched: eager {Te * 1e3:.1f} ms, graph replay {T * 1e3:.1f} ms "
@@ -144,7 +160,8 @@ def batched_extension(gep, torch, replays: int = 5) -> dict:
             "tflops_fp64": flops / T / 1e12, "capture_ms": t_capture * 1e3,
             "graphs": len(bg.members),
             "eager_ms_median": Te * 1e3, "eager_solves_per_s": len(sizes) / Te,
-            "replays_equal_eager": bool(same)}
+            "replays_equal_eager": bool(same), "worst_residual": worst_res,
+            "worst_orthogonality": worst_orth}
 
 
 def single_extension(gep, torch, name: str, warmup: int, reps: int) -> dict:
@@ -359,8 +376,8 @@ def main() -> int:
         del Y
         torch.cuda.empty_cache()
         extensions = {"m512": single_extension(gep, torch, "m512", 5, 50),
-                      "m8192": single_extension(gep, torch, "m8192", 1, 3),
-                      "batched": batched_extension(gep, torch),
+                      "m8192": single_extension(gep, torch, "m8192", 1, 5),
+                      "batched": batched_extension(gep, torch, replays=20),
                       "adjoint": adjoint_extension(gep, torch)}
         torch.cuda.empty_cache()
 
@@ -380,8 +397,14 @@ def main() -> int:
         "config": {"workload": f"gep_fp64_m{M}_decay{ell:g}_seed{seed}", "M": M,
                    "band_width": b, "job": "vectors", "precision": "fp64"},
         "tflops_fp64": tflops,
+        # context only: the one-stage LAPACK convention (17/3) M^3
+        "tflops_nominal": (17.0 / 3.0) * M ** 3 / (elapsed / args.steps) / 1e12,
         "alg_flops_per_solve": F,
         "phase_ms": phase_ms,
+        # per phase: algorithmic flops / (phase time x FP64 peak); S3 is left out
+        # (its flops depend on deflation), S2 is latency bound
+        "phase_frac_fp64_peak": {k: PHASE_FLOPS[k](M, b) / (phase_ms[k] * 1e-3) / 1e12 / PEAK_FP64
+                                 for k in PHASE_FLOPS if phase_ms.get(k, 0.0) > 0.0},
         "mixed_speedup": mixed["speedup"] if mixed else None,
         "mixed": mixed,
         "roofline": roofline,
