@@ -64,10 +64,25 @@ def cpu_baseline(M_target: int, sample: int) -> dict:
     dt = time.perf_counter() - t0
     assert r.info == 0
     scale = (M_target / sample) ** 3
-    return {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": oracle.threads(),
-            "kind": "oracle",
-            "sample": f"one full FP64 oracle solve at M={sample} ({dt:.2f} s), scaled by "
-                      f"(M/{sample})^3 to M={M_target}"}
+    out = {"value": 1.0 / (dt * scale), "unit": "solves/s", "cores": oracle.threads(),
+           "kind": "oracle",
+           "sample": f"one full FP64 oracle solve at M={sample} ({dt:.2f} s), scaled by "
+                     f"(M/{sample})^3 to M={M_target}"}
+    # vendor-CPU context (not the oracle): LAPACK dsygvd through scipy on the same
+    # sample, with the BLAS thread count it runs with
+    try:
+        import scipy.linalg
+        from threadpoolctl import threadpool_info
+        t0 = time.perf_counter()
+        scipy.linalg.eigh(A, B, driver="gvd")
+        ds = time.perf_counter() - t0
+        threads = max((i.get("num_threads", 0) for i in threadpool_info()), default=0)
+        out["lapack_context"] = {"value": 1.0 / (ds * scale), "unit": "solves/s",
+                                 "threads": threads, "seconds_at_sample": ds,
+                                 "routine": "scipy.linalg.eigh(A, B, driver='gvd')"}
+    except Exception as exc:  # context only; never fails the benchmark
+        out["lapack_context"] = {"error": repr(exc)}
+    return out
 
 
 def kernel_traffic(kernel: str, workload: str):
