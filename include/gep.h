@@ -93,6 +93,27 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
               size_t ws_bytes, int32_t* info, void* stream);
 
 /*
+ * Partial spectrum: all M eigenvalues and the eigenvectors of the k smallest.
+ * Electronic-structure calculations need eigenpairs on the order of the number
+ * of electrons (section 2.1), and the eigenvector part of a solve,
+ * T_vec = T_full - T_evo, is dominated by the back transformation (section 4.1);
+ * here the tridiagonal solver still returns all M eigenvectors (in the
+ * workspace), and only the first k go through the Q2, Q1 and L^{-T} back
+ * transformations, whose cost falls from 5M^3 to 5M^2 k flops.
+ *   k: 0..M (0: eigenvalues only, via the tridiagonal solver; M: as gep_solve).
+ *   lambda: device [M], ascending.  Y: device M x k (ldy >= max(1, M)), column j
+ *   the B-orthonormal eigenvector of lambda[j], same sign convention as gep_solve.
+ *   A, B, lda, ldb, info: as gep_solve (FP64 only).
+ *   workspace: >= gep_workspace_size_lowest(M, k) bytes, 256-byte aligned (for
+ *   k < M, one M x M buffer more than gep_solve's).
+ * Argument errors name the argument by its position (1 = M ... 12 = info).
+ */
+size_t gep_workspace_size_lowest(int64_t M, int64_t k);
+int gep_solve_lowest(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     int64_t k, double* lambda, double* Y, int64_t ldy, void* workspace,
+                     size_t ws_bytes, int32_t* info, void* stream);
+
+/*
  * Many independent problems of different orders in one call (the k-point-like
  * batches of electronic-structure codes; the paper solves one problem per run).
  * Arrays ending in _host are HOST arrays of length `batch` (orders, leading

@@ -68,6 +68,26 @@ def solve(A: torch.Tensor, B: torch.Tensor, job="vectors", prec="fp64", check_in
     return lam, (Ycm.t() if Ycm is not None else None)
 
 
+def solve_lowest(A: torch.Tensor, B: torch.Tensor, k: int, check_info=True):
+    """All eigenvalues of A y = lambda B y and the eigenvectors of the k smallest.
+    Returns (lam [M], Y [M, k]) with Y^T B Y = I_k."""
+    A = _square(A, "A")
+    B = _square(B, "B")
+    M = A.shape[0]
+    k = int(k)
+    dev = A.device
+    lam = torch.empty(M, dtype=torch.float64, device=dev)
+    Ycm = torch.empty((max(k, 0), M), dtype=torch.float64, device=dev)  # column-major M x k
+    ws = _workspace(lib().gep_workspace_size_lowest(M, k), dev)
+    info = _info(dev)
+    st = lib().gep_solve_lowest(M, _ptr(A), max(M, 1), _ptr(B), max(M, 1), k, _ptr(lam),
+                                _ptr(Ycm), max(M, 1), _ptr(ws), ws.numel(), _ptr(info), _stream())
+    check(st, "gep_solve_lowest")
+    if check_info:
+        _raise_info(info, M, "gep_solve_lowest")
+    return lam, Ycm.t()
+
+
 def reduce(A: torch.Tensor, B: torch.Tensor, check_info=True):
     """Reducer: (L, C) with B = L L^T and C = L^{-1} A L^{-T}."""
     A = _square(A, "A")

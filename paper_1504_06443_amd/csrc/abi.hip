@@ -93,6 +93,7 @@ struct Plan {
   size_t refine_bytes;
   double* coupling;
   double *L, *Linv, *tmp, *C, *T1, *band, *d, *e, *V2, *tau2, *bounds;
+  double* Zd;     // partial spectrum: the tridiagonal solver's M x M eigenvectors
   int32_t *sync, *err;
   char* scratch;  // phase scratch (reused by S1, S3, S4, S5)
   size_t scratch_bytes;
@@ -110,7 +111,7 @@ size_t phase_scratch_bytes(int64_t M, int b, bool vectors) {
   return s;
 }
 
-void carve(Plan& p, Arena& a, int64_t M, bool vectors, bool mixed = false) {
+void carve(Plan& p, Arena& a, int64_t M, bool vectors, bool mixed = false, bool partial = false) {
   p.M = M;
   p.b = default_band(M);
   p.vectors = vectors;
@@ -137,6 +138,7 @@ void carve(Plan& p, Arena& a, int64_t M, bool vectors, bool mixed = false) {
   }
   p.scratch_bytes = phase_scratch_bytes(M, p.b, vectors);
   p.scratch = a.take<char>(p.scratch_bytes);
+  p.Zd = (vectors && partial) ? a.take<double>((size_t)M * M) : nullptr;
   p.refine_ws = nullptr;
   p.refine_bytes = 0;
   p.coupling = nullptr;
@@ -199,18 +201,24 @@ int guarded(F&& f) {
 // prof: record the phase events.  mixed (vectors only): the interior GEMM tiles of
 // R1, R2-4, S1, S5 and R5 run in FP32 arithmetic, S2-S4 and the diagonal blocks of
 // the Cholesky stay FP64, and the eigenpairs are then refined in FP64 (REF).
+// nvec: with vectors, the number of eigenvectors wanted (those of the nvec smallest
+// eigenvalues; all when nvec < 0 or nvec >= M).  Fewer than M: the tridiagonal
+// solver writes all M eigenvectors to the workspace, and only the first nvec
+// columns are copied to Y and taken through the back transformations.
 void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
                double* lambda, double* Y, int64_t ldy, bool vectors, void* workspace,
                size_t ws_bytes, int32_t* info, hipStream_t s, bool coop, bool prof_on,
-               bool mixed = false) {
+               bool mixed = false, int64_t nvec = -1) {
   fill_i32(info, 1, 0, s);
   if (M == 0) return;
   mixed = mixed && vectors;
+  const int64_t k = (nvec < 0 || nvec > M) ? M : nvec;
+  const bool partial = vectors && k < M;
   Plan p;
   Arena a;
   a.base = (char*)workspace;
   a.cap = ws_bytes;
-  carve(p, a, M, vectors, mixed);
+  carve(p, a, M, vectors, mixed, partial);
   Prof prof(s);
   Prof* pp = prof_on ? &prof : nullptr;
   const MathMode trailing = mixed ? MathMode::Fp32 : MathMode::Fp64;
@@ -235,20 +243,21 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
   {
     MathScope fp64(MathMode::Fp64);
     Arena sa = scratch_arena(p);
-    stedc(M, p.d, p.e, lambda, Y, ldy, info, sa, s);
+    stedc(M, p.d, p.e, lambda, partial ? p.Zd : Y, partial ? M : ldy, info, sa, s);
+    if (partial && k > 0) copy_matrix(M, k, p.Zd, M, Y, ldy, s);
   }
   if (pp) pp->mark(5);
   {
     Arena sa = scratch_arena(p);
-    apply_q2(chase_of(p), Y, ldy, M, sa, s);
+    apply_q2(chase_of(p), Y, ldy, k, sa, s);
   }
   if (pp) pp->mark(6);
   {
     Arena sa = scratch_arena(p);
-    apply_q1(band_of(p), Y, ldy, M, sa, s);
+    apply_q1(band_of(p), Y, ldy, k, sa, s);
   }
   if (pp) pp->mark(7);
-  trsm_llt(Tri{p.L, M, p.Linv, 0}, M, Y, ldy, M, p.tmp, s);
+  trsm_llt(Tri{p.L, M, p.Linv, 0}, M, Y, ldy, k, p.tmp, s);
   if (pp) pp->mark(8);
   if (mixed) {
     // L and C are no longer needed: they are the refinement's M x M scratch
@@ -258,8 +267,10 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
     refine(M, A, lda, B, ldb, Y, ldy, lambda, p.L, p.C, ra, p.coupling, s);
   }
   if (pp) pp->mark(9);
-  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
-  GEP_LAUNCH_CHECK();
+  if (k > 0) {
+    hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)k), dim3(256), 0, s, M, Y, ldy);
+    GEP_LAUNCH_CHECK();
+  }
   if (pp) pp->mark(10);
 }
 
@@ -402,6 +413,40 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
   return guarded([&]() -> int {
     solve_one(M, A, lda, B, ldb, lambda, Y, ldy, job == GEP_JOB_VECTORS, workspace, ws_bytes, info,
               s, true, true, prec == GEP_PREC_MIXED);
+    return GEP_OK;
+  });
+}
+
+size_t gep_workspace_size_lowest(int64_t M, int64_t k) {
+  if (M <= 0) return 256;
+  Plan p;
+  Arena a;
+  a.dry = true;
+  carve(p, a, M, true, false, k >= 0 && k < M);
+  return a.used + 256;
+}
+
+int gep_solve_lowest(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     int64_t k, double* lambda, double* Y, int64_t ldy, void* workspace,
+                     size_t ws_bytes, int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (k < 0 || k > M) return bad(6);
+  if (M > 0 && !lambda) return bad(7);
+  if (k > 0 && !Y) return bad(8);
+  if (ldy < m1) return bad(9);
+  if (!info) return bad(12);
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(10);
+  if (ws_bytes < gep_workspace_size_lowest(M, k)) return GEP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    solve_one(M, A, lda, B, ldb, lambda, Y, ldy, true, workspace, ws_bytes, info, s, true, true,
+              false, k);
     return GEP_OK;
   });
 }

@@ -618,7 +618,7 @@ void apply_q1(const BandReduction& r, double* Z, int64_t ldz, int64_t ncols, Are
               hipStream_t s) {
   const int64_t N = r.n;
   const int b = r.b;
-  if (N <= b) return;
+  if (N <= b || ncols <= 0) return;
   const int64_t npan = cdiv(N - b, b);  // panels with rows below the band: col0 + b < N
   const int64_t Wmax = (int64_t)QG * b;
   double* Vg = ws.take<double>((size_t)N * Wmax);

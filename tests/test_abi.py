@@ -119,3 +119,39 @@ def test_probe_names_and_bad_index(lib):
     assert lib.gep_probe_name(4) is None
     assert lib.gep_probe_read(4, None, None, None) == -1
     assert lib.gep_last_bad_arg() == 1
+
+
+def _lowest(lib, M, k, lda=None, A=FAKE, B=FAKE, lam=FAKE, Y=FAKE, ldy=None, ws=P(0x200000),
+            wsb=None, info=FAKE):
+    lda = M if lda is None else lda
+    ldy = max(M, 1) if ldy is None else ldy
+    wsb = lib.gep_workspace_size_lowest(max(M, 0), k) if wsb is None else wsb
+    return lib.gep_solve_lowest(M, A, lda, B, max(M, 1), k, lam, Y, ldy, ws, wsb, info, None)
+
+
+@pytest.mark.parametrize("kwargs,arg", [
+    (dict(M=-1, k=0), 1),
+    (dict(M=10, k=3, A=P(0)), 2),
+    (dict(M=10, k=3, lda=9), 3),
+    (dict(M=10, k=3, B=P(0)), 4),
+    (dict(M=10, k=-1), 6),
+    (dict(M=10, k=11), 6),
+    (dict(M=10, k=3, lam=P(0)), 7),
+    (dict(M=10, k=3, Y=P(0)), 8),
+    (dict(M=10, k=3, ldy=9), 9),
+    (dict(M=10, k=3, ws=P(0x200010)), 10),
+    (dict(M=10, k=3, info=P(0)), 12),
+])
+def test_solve_lowest_rejects_bad_arguments(lib, kwargs, arg):
+    assert _lowest(lib, **kwargs) == -1
+    assert lib.gep_last_bad_arg() == arg
+
+
+def test_solve_lowest_workspace(lib):
+    M = 300
+    # k < M holds the tridiagonal solver's M x M eigenvectors on top of gep_solve's needs
+    assert lib.gep_workspace_size_lowest(M, M) == lib.gep_workspace_size(M, 1, 0)
+    assert lib.gep_workspace_size_lowest(M, 10) >= lib.gep_workspace_size(M, 1, 0) + 8 * M * M
+    # k = 0 needs no Y; the call then fails only at the workspace check
+    need = lib.gep_workspace_size_lowest(M, 0)
+    assert _lowest(lib, M, 0, Y=P(0), wsb=need - 1) == -2

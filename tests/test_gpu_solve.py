@@ -114,3 +114,46 @@ def test_solve_indefinite_B_reports_info(gpu):
     B[40, 40] = -1.0
     with pytest.raises(torch.linalg.LinAlgError):
         _gep().solve(to_gpu(A), to_gpu(B))
+
+
+@pytest.mark.parametrize("M,k", [(1, 1), (5, 0), (64, 17), (300, 150), (700, 1), (700, 700)])
+def test_solve_lowest_matches_oracle(gpu, M, k):
+    """Partial spectrum: all eigenvalues and the eigenvectors of the k smallest,
+    against the oracle (eigenvalues, B-orthogonality, residual, eigenspaces of the
+    k smallest) and against the full solve's first k columns."""
+    say(f"[lowest] M={M} k={k}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 900 + M)
+    lam, Y = _gep().solve_lowest(to_gpu(A), to_gpu(B), k)
+    lam, Y = to_np(lam), to_np(Y)
+    assert Y.shape == (M, k)
+    r = oracle.solve(A, B)
+    n1 = r.norm1
+    assert np.abs(lam - r.lam).max() / n1 <= TOL_LAMBDA
+    if k:
+        assert np.abs(Y.T @ B @ Y - np.eye(k)).max() <= TOL_ORTH
+        res = (np.abs(A @ Y - B @ Y * lam[None, :k]).sum(axis=0).max()
+               / (n1 * np.abs(Y).sum(axis=0).max()))
+        assert res <= TOL_RES, res
+        assert max_subspace_sine(Y, r.Y[:, :k], B, r.lam[:k], 1e-8 * n1) <= 1e-11 * n1
+        lam_f, Y_f = _gep().solve(to_gpu(A), to_gpu(B))
+        assert np.array_equal(to_np(lam_f), lam)
+        assert np.abs(to_np(Y_f)[:, :k] - Y).max() <= 1e-10 * np.abs(Y).max()
+
+
+def test_solve_lowest_band64(gpu):
+    """Partial spectrum at band width 64 (ragged order, k not a multiple of 16):
+    residual and B-orthogonality of the k vectors, eigenvalues equal to the full
+    solve's, vectors equal to its first k columns to rounding."""
+    M, k = 2113, 601
+    say(f"[lowest] M={M} k={k}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 500 + M)
+    lam, Y = _gep().solve_lowest(to_gpu(A), to_gpu(B), k)
+    lam, Y = to_np(lam), to_np(Y)
+    n1 = np.abs(A).sum(axis=0).max()
+    assert np.abs(Y.T @ B @ Y - np.eye(k)).max() <= TOL_ORTH
+    res = (np.abs(A @ Y - B @ Y * lam[None, :k]).sum(axis=0).max()
+           / (n1 * np.abs(Y).sum(axis=0).max()))
+    assert res <= TOL_RES, res
+    lam_f, Y_f = _gep().solve(to_gpu(A), to_gpu(B))
+    assert np.array_equal(to_np(lam_f), lam)
+    assert np.abs(to_np(Y_f)[:, :k] - Y).max() <= 1e-10 * np.abs(Y).max()
