@@ -78,6 +78,24 @@ __device__ bool grid_barrier(const PanelArgs& a, unsigned target) {
   return ok != 0;
 }
 
+// Sum of the partials gg = qt, qt + 4, qt + 8, ... < G of column q, added in
+// that order; K loads are issued before the first is used.
+template <int K>
+__device__ inline double gather_partials(const double* part, int G, int qt, int q) {
+  double s = 0.0;
+  for (int gg0 = qt; gg0 < G; gg0 += 4 * K) {
+    double v[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int gg = gg0 + 4 * k;
+      v[k] = cld(&part[(size_t)(gg < G ? gg : G - 1) * MAXB + q]);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) s += (gg0 + 4 * k < G) ? v[k] : 0.0;
+  }
+  return s;
+}
+
 __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
   extern __shared__ double Ps[];  // rows_per x (MAXB + 1), row-major
   __shared__ double wv[MAXB];
@@ -98,16 +116,27 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
     const int buf = c & 1;
     double* part = a.part + (size_t)buf * G * MAXB;
     double* top = a.top + buf * MAXB;
-    // partial sums: thread (q, lane4) sums rows lane4, lane4+4, ...
+    // partial sums: thread (q, sub) sums rows sub, sub + 4, ... of the slice that
+    // lie at or below the panel's top row c (strictly below it for column c's own
+    // norm), in eight independent sums so that eight row pairs are in flight
     {
       const int q = tid >> 2, sub = tid & 3;
       double acc = 0.0;
       if (q >= c && q < w) {
-        for (int i = sub; i < nr; i += 4) {
-          const int64_t gi = r0 + i;
-          if (gi < c || (q == c && gi == c)) continue;
-          acc += Ps[i * LDP + c] * Ps[i * LDP + q];
+        const int64_t lo = (q == c) ? (int64_t)c + 1 : (int64_t)c;
+        int i = sub;
+        if (r0 + i < lo) i += (int)((lo - r0 - i + 3) / 4) * 4;
+        double s8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        for (; i < nr; i += 32) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int iu = i + 4 * u;
+            const int ii = iu < nr ? iu : nr - 1;  // clamped row, in the slice
+            const double x = Ps[ii * LDP + c] * Ps[ii * LDP + q];
+            s8[u] += iu < nr ? x : 0.0;
+          }
         }
+        acc = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
       }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
@@ -120,25 +149,17 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
     if (!grid_barrier(a, (unsigned)(G * (c + 1)))) return;
     // Every workgroup reduces the partials in the same fixed order, so all derive
     // the identical reflector.  Thread (quarter, q) sums partials quarter,
-    // quarter + 4, ... of column q; its remote loads are issued eight at a time (a
-    // serial chain of G remote loads per column was the panel's main cost at large
-    // G), and the quarter sums are added in LDS in a fixed order.  The top row is
-    // fetched in the same round.
+    // quarter + 4, ... of column q, with all of its remote loads in flight at once
+    // for G <= 128 (each round of remote loads costs a full memory latency), and
+    // the quarter sums are added in LDS in a fixed order.  The top row is fetched
+    // in the same round.
     {
       const int q = tid & (MAXB - 1), qt = tid >> 6;
       double s = 0.0;
       if (q >= c && q < w) {
-        for (int gg0 = qt; gg0 < G; gg0 += 32) {
-          double v[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const int gg = gg0 + 4 * k;
-            v[k] = cld(&part[(size_t)(gg < G ? gg : G - 1) * MAXB + q]);
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k) s += (gg0 + 4 * k < G) ? v[k] : 0.0;
-        }
-        if (qt == 0) tops[q] = cld(&top[q]);
+        const double tq = qt == 0 ? cld(&top[q]) : 0.0;
+        s = G <= 32 ? gather_partials<8>(part, G, qt, q) : gather_partials<32>(part, G, qt, q);
+        if (qt == 0) tops[q] = tq;
       }
       red[qt][q] = s;
     }
