@@ -91,19 +91,41 @@ __device__ void house(int L, double* x, double* sh, double& beta_out, double& ta
   __syncthreads();
 }
 
+// Every loop over a block column or row below has a fixed trip count of
+// PER = MAXB / 4: each thread first reads all of its (up to PER) operands from
+// LDS, with indices past the end clamped to a valid element, and only then
+// computes and writes, so the reads' latencies overlap instead of adding up.
+constexpr int PER = MAXB / (NT / 64);
+
+// out[x] = scale * sum_{y < ny} M[x * sx + y * sy] w[y] for x < nx: four threads
+// per x, each summing y = q, q + 4, ... pairwise; the four partials are added
+// in a fixed order.
+__device__ inline void matvec4(int nx, int ny, const double* M, int sx, int sy, const double* w,
+                               double scale, double* out) {
+  const int tid = threadIdx.x, x = tid >> 2, q = tid & 3;
+  const int xc = x < nx ? x : 0;
+  double t[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int y = q + 4 * m;
+    const int yc = y < ny ? y : 0;
+    const double prod = M[xc * sx + yc * sy] * w[yc];
+    t[m] = y < ny ? prod : 0.0;
+  }
+#pragma unroll
+  for (int h = PER / 2; h >= 1; h >>= 1)
+#pragma unroll
+    for (int m = 0; m < h; ++m) t[m] += t[m + h];
+  const double acc = quad_sum(t[0]);
+  if (x < nx && q == 0) out[x] = scale * acc;
+}
+
 // D (L x L symmetric, full in LDS, ld LDS_LD) <- H D H, H = I - tau v v^T.
 // 4 threads per row for the matrix-vector product.
 __device__ void two_sided(int L, double* D, const double* v, double tau, double* p, double* sh) {
   const int tid = threadIdx.x;
   if (tau == 0.0) return;
-  {
-    const int row = tid >> 2, q = tid & 3;
-    double acc = 0.0;
-    if (row < L)
-      for (int j = q; j < L; j += 4) acc += D[row + j * LDS_LD] * v[j];
-    acc = quad_sum(acc);
-    if (row < L && q == 0) p[row] = tau * acc;
-  }
+  matvec4(L, L, D, 1, LDS_LD, v, tau, p);
   __syncthreads();
   if (tid < 64) {
     double s = 0.0;
@@ -114,12 +136,23 @@ __device__ void two_sided(int L, double* D, const double* v, double tau, double*
   __syncthreads();
   const double a = sh[3];
   {
-    const int i = tid & 63;
+    const int i = tid & 63, j0 = tid >> 6;
     if (i < L) {
       const double vi = v[i], pi = p[i] - a * vi;
-      for (int j = tid >> 6; j < L; j += NT / 64) {
-        const double pj = p[j] - a * v[j];
-        D[i + j * LDS_LD] -= vi * pj + pi * v[j];
+      double d[PER], pv[PER], vv[PER];
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = j0 + 4 * m;
+        const int jc = j < L ? j : 0;
+        d[m] = D[i + jc * LDS_LD];
+        pv[m] = p[jc];
+        vv[m] = v[jc];
+      }
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = j0 + 4 * m;
+        const double pj = pv[m] - a * vv[m];
+        if (j < L) D[i + j * LDS_LD] = d[m] - (vi * pj + pi * vv[m]);
       }
     }
   }
@@ -211,7 +244,6 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
       // the loads' latencies overlap instead of adding up.
       {
         const int i = tid & 63, j0 = tid >> 6;
-        constexpr int PER = MAXB / (NT / 64);  // 16 elements per thread and block
         double xd[PER], xe[PER];
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
@@ -250,23 +282,28 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
       double beta, tau;
       if (k == 0) {
         house(L, v, sh, beta, tau);
-        if (tid == 0) cst(&band[1 + s * ld], beta);
-        if (tid >= 1 && tid < L) cst(&band[(1 + tid) + s * ld], 0.0);
       } else {
         // E <- E (I - tau_prev vprev vprev^T)
         if (tau_prev != 0.0) {
-          const int row = tid >> 2, q = tid & 3;
-          double acc = 0.0;
-          if (row < L)
-            for (int j = q; j < Lprev; j += 4) acc += Es[row + j * LDS_LD] * vprev[j];
-          acc = quad_sum(acc);
-          if (row < L && q == 0) p[row] = tau_prev * acc;
+          matvec4(L, Lprev, Es, 1, LDS_LD, vprev, tau_prev, p);
           __syncthreads();
           {
-            const int i = tid & 63;
+            const int i = tid & 63, j0 = tid >> 6;
             if (i < L) {
               const double pi = p[i];
-              for (int j = tid >> 6; j < Lprev; j += NT / 64) Es[i + j * LDS_LD] -= pi * vprev[j];
+              double e[PER], vv[PER];
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + 4 * m;
+                const int jc = j < Lprev ? j : 0;
+                e[m] = Es[i + jc * LDS_LD];
+                vv[m] = vprev[jc];
+              }
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + 4 * m;
+                if (j < Lprev) Es[i + j * LDS_LD] = e[m] - pi * vv[m];
+              }
             }
           }
           __syncthreads();
@@ -276,39 +313,73 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
         __syncthreads();
         house(L, v, sh, beta, tau);
         if (tau != 0.0) {
-          const int col = tid >> 2, q = tid & 3;
-          double acc = 0.0;
-          if (col >= 1 && col < Lprev)
-            for (int i = q; i < L; i += 4) acc += v[i] * Es[i + col * LDS_LD];
-          acc = quad_sum(acc);
-          if (col >= 1 && col < Lprev && q == 0) p[col] = tau * acc;
+          // p[col] = tau v^T E(:, col); column 0 is replaced by beta e_1 below
+          matvec4(Lprev, L, Es, LDS_LD, 1, v, tau, p);
           __syncthreads();
           {
-            const int i = tid & 63;
+            const int i = tid & 63, j0 = tid >> 6;
             if (i < L) {
               const double vi = v[i];
-              for (int j = 1 + (tid >> 6); j < Lprev; j += NT / 64) Es[i + j * LDS_LD] -= vi * p[j];
+              double e[PER], pp[PER];
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + 4 * m;
+                const int jc = j < Lprev ? j : 0;
+                e[m] = Es[i + jc * LDS_LD];
+                pp[m] = p[jc];
+              }
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + 4 * m;
+                if (j >= 1 && j < Lprev) Es[i + j * LDS_LD] = e[m] - vi * pp[m];
+              }
             }
           }
         }
         if (tid == 0) Es[0] = beta;
         if (tid >= 1 && tid < L) Es[tid] = 0.0;
         __syncthreads();
-        {
-          const int i = tid & 63;
-          if (i < L)
-            for (int j = tid >> 6; j < Lprev; j += NT / 64)
-              cst(&band[(b + i - j) + (c + j) * ld], Es[i + j * LDS_LD]);
+      }
+      // diagonal block rows/cols r .. r+L-1 <- H D H.  The task's band stores are
+      // all issued after its arithmetic: the wait for a load's data also waits for
+      // every store issued before that load, and the release below has to wait
+      // for the stores anyway.
+      if (tau != 0.0) two_sided(L, Ds, v, tau, p, sh);
+      if (k == 0) {
+        if (tid == 0) cst(&band[1 + s * ld], beta);
+        if (tid >= 1 && tid < L) cst(&band[(1 + tid) + s * ld], 0.0);
+      } else {
+        const int i = tid & 63, j0 = tid >> 6;
+        if (i < L) {
+          double e[PER];
+#pragma unroll
+          for (int m = 0; m < PER; ++m) {
+            const int j = j0 + 4 * m;
+            e[m] = Es[i + (j < Lprev ? j : 0) * LDS_LD];
+          }
+#pragma unroll
+          for (int m = 0; m < PER; ++m) {
+            const int j = j0 + 4 * m;
+            if (j < Lprev) cst(&band[(b + i - j) + (c + j) * ld], e[m]);
+          }
         }
       }
-      // diagonal block rows/cols r .. r+L-1 <- H D H
       if (tau != 0.0) {
-        two_sided(L, Ds, v, tau, p, sh);
         {
-          const int i = tid & 63;
-          if (i < L)
-            for (int j = tid >> 6; j <= i; j += NT / 64)
-              cst(&band[(i - j) + (r + j) * ld], Ds[i + j * LDS_LD]);
+          const int i = tid & 63, j0 = tid >> 6;
+          if (i < L) {
+            double d[PER];
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+              const int j = j0 + 4 * m;
+              d[m] = Ds[i + (j <= i ? j : 0) * LDS_LD];
+            }
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+              const int j = j0 + 4 * m;
+              if (j <= i) cst(&band[(i - j) + (r + j) * ld], d[m]);
+            }
+          }
         }
       }
       // store the reflector in its Q2 block (consumed by a later kernel)
