@@ -857,20 +857,23 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
     const double* t0 = Tb + (4 * r + l4) * VLD + l15;
     const double* t1 = Tb + (16 + 4 * r + l4) * VLD + l15;
     X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[0], W0[r], X0, 0, 0, 0);
-    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[0], W1[r], X0, 0, 0, 0);
     X1 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[16], W1[r], X1, 0, 0, 0);
+    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[0], W1[r], X0, 0, 0, 0);
   }
 
-  // Z += V X: window tile u meets c tile 0 for u <= 4 and c tile 1 for u >= 1
+  // Z += V X: window tile u meets c tile 0 for u <= 4 and c tile 1 for u >= 1.
+  // Consecutive products go to different window tiles (k step outermost).
 #pragma unroll
-  for (int u = 0; u < 6; ++u) {
+  for (int r = 0; r < 4; ++r) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int u = 0; u <= 4; ++u) {
       const double* vr = V + (16 * u + l15) * VLD + 4 * r + l4;
-      if (u <= 4)
-        Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], X0[r], Z[(S0 + u) & 7], 0, 0, 0);
-      if (u >= 1)
-        Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], X1[r], Z[(S0 + u) & 7], 0, 0, 0);
+      Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], X0[r], Z[(S0 + u) & 7], 0, 0, 0);
+    }
+#pragma unroll
+    for (int u = 1; u < 6; ++u) {
+      const double* vr = V + (16 * u + l15) * VLD + 4 * r + l4;
+      Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], X1[r], Z[(S0 + u) & 7], 0, 0, 0);
     }
   }
   if (more) vt_commit(st, Vs[cur ^ 1], Tt[cur ^ 1]);
