@@ -114,6 +114,24 @@ int gep_solve_lowest(int64_t M, const double* A, int64_t lda, const double* B, i
                      size_t ws_bytes, int32_t* info, void* stream);
 
 /*
+ * Cholesky-free reducer (section 3.1, Eqs. 7-9): instead of B = L L^T, the
+ * symmetric eigenproblem of B itself, B W = W D, is solved by the same two-stage
+ * SEP path; the reduced matrix is C = (W D^{-1/2})^T A (W D^{-1/2}) and the
+ * eigenvectors are Y = W D^{-1/2} Z with C Z = Z Lambda.  Two SEP solves and three
+ * M^3 GEMMs: slower than gep_solve on one GPU, but no triangular factor or solve.
+ *   A, B, lda, ldb, lambda, Y, ldy: as gep_solve with job = GEP_JOB_VECTORS (FP64).
+ *   workspace: >= gep_workspace_size_cholfree(M) bytes, 256-byte aligned (one
+ *   M x M buffer and M doubles more than gep_solve's).
+ *   info: as gep_solve, except that M + c means that c eigenvalues of B are not
+ *   positive (B is not positive definite; Y and lambda are then meaningless).
+ * Argument errors name the argument by its position (1 = M ... 11 = info).
+ */
+size_t gep_workspace_size_cholfree(int64_t M);
+int gep_solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                       double* lambda, double* Y, int64_t ldy, void* workspace, size_t ws_bytes,
+                       int32_t* info, void* stream);
+
+/*
  * Many independent problems of different orders in one call (the k-point-like
  * batches of electronic-structure codes; the paper solves one problem per run).
  * Arrays ending in _host are HOST arrays of length `batch` (orders, leading

@@ -88,6 +88,30 @@ def solve_lowest(A: torch.Tensor, B: torch.Tensor, k: int, check_info=True):
     return lam, Ycm.t()
 
 
+def solve_cholfree(A: torch.Tensor, B: torch.Tensor, check_info=True):
+    """All eigenpairs of A y = lambda B y through the Cholesky-free reducer
+    (B W = W D by the SEP solver, C = D^-1/2 W^T A W D^-1/2, Y = W D^-1/2 Z).
+    Returns (lam, Y) with Y^T B Y = I."""
+    A = _square(A, "A")
+    B = _square(B, "B")
+    M = A.shape[0]
+    dev = A.device
+    lam = torch.empty(M, dtype=torch.float64, device=dev)
+    Ycm = torch.empty((M, M), dtype=torch.float64, device=dev)  # column-major
+    ws = _workspace(lib().gep_workspace_size_cholfree(M), dev)
+    info = _info(dev)
+    st = lib().gep_solve_cholfree(M, _ptr(A), max(M, 1), _ptr(B), max(M, 1), _ptr(lam), _ptr(Ycm),
+                                  max(M, 1), _ptr(ws), ws.numel(), _ptr(info), _stream())
+    check(st, "gep_solve_cholfree")
+    if check_info:
+        v = int(info.item())
+        if v > M:
+            raise torch.linalg.LinAlgError(f"gep_solve_cholfree: B is not positive definite "
+                                           f"({v - M} eigenvalues of B are not positive)")
+        _raise_info(info, M, "gep_solve_cholfree")
+    return lam, Ycm.t()
+
+
 def reduce(A: torch.Tensor, B: torch.Tensor, check_info=True):
     """Reducer: (L, C) with B = L L^T and C = L^{-1} A L^{-T}."""
     A = _square(A, "A")

@@ -62,6 +62,30 @@ __global__ void band_copy_out(int64_t n, int b, const double* __restrict__ band,
   for (int d = 0; d <= b; ++d) out[d + j * ldo] = (j + d < n) ? band[d + j * ldw] : 0.0;
 }
 
+// W(:, j) <- W(:, j) / sqrt(d_j): the columns of W D^{-1/2} (section 3.1, Eqs. 8
+// and 9); a column whose d_j is not positive is zeroed.
+__global__ void scale_cols_rsqrt(int64_t n, const double* __restrict__ d, double* __restrict__ W,
+                                 int64_t ldw) {
+  const double dj = d[blockIdx.x];
+  const double sc = dj > 0.0 ? 1.0 / sqrt(dj) : 0.0;
+  double* w = W + (int64_t)blockIdx.x * ldw;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) w[i] *= sc;
+}
+
+// info <- n + (number of d_i that are not positive), unless info is already set.
+__global__ void count_nonpositive(int64_t n, const double* __restrict__ d, int32_t* info) {
+  __shared__ int cnt[256];
+  int c = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) c += (d[i] > 0.0) ? 0 : 1;
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) cnt[threadIdx.x] += cnt[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && cnt[0] > 0) atomicCAS(info, 0, (int32_t)(n + cnt[0]));
+}
+
 // ---------------------------------------------------------------- profiling
 constexpr int NPHASE = 10;
 bool g_prof = false;
@@ -274,6 +298,103 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
   if (pp) pp->mark(10);
 }
 
+// Eigenvalues (ascending) and all eigenvectors of the symmetric matrix whose
+// lower triangle is in p.C (destroyed): the SEP path S1 .. S5 into lam and Z.
+void sep_vectors(const Plan& p, double* lam, double* Z, int64_t ldz, int32_t* info,
+                 hipStream_t s) {
+  const int64_t M = p.M;
+  {
+    Arena sa = scratch_arena(p);
+    BandReduction r = band_of(p);
+    r.coop = true;
+    sy2sb(r, sa, s);
+  }
+  sb2st(chase_of(p), s);
+  {
+    Arena sa = scratch_arena(p);
+    stedc(M, p.d, p.e, lam, Z, ldz, info, sa, s);
+  }
+  {
+    Arena sa = scratch_arena(p);
+    apply_q2(chase_of(p), Z, ldz, M, sa, s);
+  }
+  {
+    Arena sa = scratch_arena(p);
+    apply_q1(band_of(p), Z, ldz, M, sa, s);
+  }
+}
+
+// Extra workspace of the Cholesky-free solve beyond the plan: W (M x M) and D (M).
+void carve_cholfree(Plan& p, Arena& a, int64_t M, double** W, double** dB) {
+  carve(p, a, M, true);
+  *W = a.take<double>((size_t)M * M);
+  *dB = a.take<double>((size_t)M);
+}
+
+// Cholesky-free reducer (section 3.1, Eqs. 7-9): the SEP of B itself, B W = W D,
+// replaces the Cholesky factorization; the reduced matrix is
+// C = (W D^{-1/2})^T A (W D^{-1/2}) and the eigenvectors are Y = W D^{-1/2} Z, where
+// C Z = Z Lambda.  Both SEPs run through the same two-stage path.  Phase events:
+// 0 start, 1 after the SEP of B, 2 after C is formed, 3 after the SEP of C, 4 .. 10
+// after Y.
+void solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                    double* lambda, double* Y, int64_t ldy, void* workspace, size_t ws_bytes,
+                    int32_t* info, hipStream_t s, bool prof_on) {
+  fill_i32(info, 1, 0, s);
+  if (M == 0) return;
+  Plan p;
+  Arena a;
+  a.base = (char*)workspace;
+  a.cap = ws_bytes;
+  double *W = nullptr, *dB = nullptr;
+  carve_cholfree(p, a, M, &W, &dB);
+  Prof prof(s);
+  Prof* pp = prof_on ? &prof : nullptr;
+  MathScope fp64(MathMode::Fp64);
+  if (pp) pp->mark(0);
+  // B W = W D
+  symmetrize_from_lower(M, B, ldb, p.C, M, s);
+  sep_vectors(p, dB, W, M, info, s);
+  if (pp) pp->mark(1);
+  // W <- W D^{-1/2}; B is positive definite iff every d_j > 0
+  hipLaunchKernelGGL(count_nonpositive, dim3(1), dim3(256), 0, s, M, (const double*)dB, info);
+  GEP_LAUNCH_CHECK();
+  hipLaunchKernelGGL(scale_cols_rsqrt, dim3((unsigned)M), dim3(256), 0, s, M, (const double*)dB, W,
+                     M);
+  GEP_LAUNCH_CHECK();
+  // C = W^T (A W), lower triangle; p.L is the M x M product scratch
+  symmetrize_from_lower(M, A, lda, p.C, M, s);
+  {
+    Gemm g;
+    g.m = M; g.n = M; g.k = M;
+    g.A = p.C; g.lda = M; g.B = W; g.ldb = M; g.C = p.L; g.ldc = M;
+    gemm(g, s);
+  }
+  {
+    Gemm g;
+    g.transA = true;
+    g.uplo = 1;
+    g.m = M; g.n = M; g.k = M;
+    g.A = W; g.lda = M; g.B = p.L; g.ldb = M; g.C = p.C; g.ldc = M;
+    gemm(g, s);
+  }
+  if (pp) pp->mark(2);
+  // C Z = Z Lambda, Z in p.L
+  sep_vectors(p, lambda, p.L, M, info, s);
+  if (pp) pp->mark(3);
+  // Y = (W D^{-1/2}) Z
+  {
+    Gemm g;
+    g.m = M; g.n = M; g.k = M;
+    g.A = W; g.lda = M; g.B = p.L; g.ldb = M; g.C = Y; g.ldc = ldy;
+    gemm(g, s);
+  }
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
+  GEP_LAUNCH_CHECK();
+  if (pp)
+    for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
+}
+
 // ---------------------------------------------------------------- batches
 // Instances run on NSTREAM worker streams forked from the caller's stream with
 // events (so the whole batch can be captured in one graph).  Longest-processing-
@@ -447,6 +568,39 @@ int gep_solve_lowest(int64_t M, const double* A, int64_t lda, const double* B, i
   return guarded([&]() -> int {
     solve_one(M, A, lda, B, ldb, lambda, Y, ldy, true, workspace, ws_bytes, info, s, true, true,
               false, k);
+    return GEP_OK;
+  });
+}
+
+size_t gep_workspace_size_cholfree(int64_t M) {
+  if (M <= 0) return 256;
+  Plan p;
+  Arena a;
+  a.dry = true;
+  double *W = nullptr, *dB = nullptr;
+  carve_cholfree(p, a, M, &W, &dB);
+  return a.used + 256;
+}
+
+int gep_solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                       double* lambda, double* Y, int64_t ldy, void* workspace, size_t ws_bytes,
+                       int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (M > 0 && !lambda) return bad(6);
+  if (M > 0 && !Y) return bad(7);
+  if (ldy < m1) return bad(8);
+  if (!info) return bad(11);
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(9);
+  if (ws_bytes < gep_workspace_size_cholfree(M)) return GEP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    solve_cholfree(M, A, lda, B, ldb, lambda, Y, ldy, workspace, ws_bytes, info, s, true);
     return GEP_OK;
   });
 }

@@ -155,3 +155,39 @@ def test_solve_lowest_workspace(lib):
     # k = 0 needs no Y; the call then fails only at the workspace check
     need = lib.gep_workspace_size_lowest(M, 0)
     assert _lowest(lib, M, 0, Y=P(0), wsb=need - 1) == -2
+
+
+
+def _cholfree(lib, M, lda=None, A=FAKE, B=FAKE, lam=FAKE, Y=FAKE, ldy=None, ws=P(0x200000),
+              wsb=None, info=FAKE):
+    lda = M if lda is None else lda
+    ldy = max(M, 1) if ldy is None else ldy
+    wsb = lib.gep_workspace_size_cholfree(max(M, 0)) if wsb is None else wsb
+    return lib.gep_solve_cholfree(M, A, lda, B, max(M, 1), lam, Y, ldy, ws, wsb, info, None)
+
+
+@pytest.mark.parametrize("kwargs,arg", [
+    (dict(M=-1), 1),
+    (dict(M=10, A=P(0)), 2),
+    (dict(M=10, lda=9), 3),
+    (dict(M=10, B=P(0)), 4),
+    (dict(M=10, lam=P(0)), 6),
+    (dict(M=10, Y=P(0)), 7),
+    (dict(M=10, ldy=9), 8),
+    (dict(M=10, ws=P(0x200010)), 9),
+    (dict(M=10, ws=P(0)), 9),
+    (dict(M=10, info=P(0)), 11),
+])
+def test_solve_cholfree_rejects_bad_arguments(lib, kwargs, arg):
+    assert _cholfree(lib, **kwargs) == -1
+    assert lib.gep_last_bad_arg() == arg
+
+
+def test_solve_cholfree_workspace(lib):
+    M = 300
+    # one M x M buffer (W) and M doubles (D) on top of gep_solve's needs
+    base = lib.gep_workspace_size(M, 1, 0)
+    assert lib.gep_workspace_size_cholfree(M) >= base + 8 * M * M + 8 * M
+    assert lib.gep_workspace_size_cholfree(0) == 256
+    need = lib.gep_workspace_size_cholfree(M)
+    assert _cholfree(lib, M, wsb=need - 1) == -2

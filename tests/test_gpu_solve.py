@@ -157,3 +157,65 @@ def test_solve_lowest_band64(gpu):
     lam_f, Y_f = _gep().solve(to_gpu(A), to_gpu(B))
     assert np.array_equal(to_np(lam_f), lam)
     assert np.abs(to_np(Y_f)[:, :k] - Y).max() <= 1e-10 * np.abs(Y).max()
+
+
+def _cond(B):
+    w = np.linalg.eigvalsh(B)
+    return w[-1] / w[0]
+
+
+@pytest.mark.parametrize("M", [1, 2, 17, 64, 129, 300, 700])
+def test_solve_cholfree_matches_oracle(gpu, M):
+    """Cholesky-free reducer (B W = W D by the SEP solver, C = D^-1/2 W^T A W D^-1/2,
+    Y = W D^-1/2 Z) against the oracle: eigenvalues, B-orthogonality, residual and
+    eigenspaces, and eigenvalues against the Cholesky path.  Y^T B Y - I carries
+    the SEP's orthogonality error of W times cond(B) (through D^-1/2), so its bound
+    is scaled by cond(B)."""
+    say(f"[cholfree] M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 700 + M)
+    lam, Y = _gep().solve_cholfree(to_gpu(A), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    r = oracle.solve(A, B)
+    n1 = r.norm1
+    kappa = _cond(B)
+    assert np.all(np.diff(lam) >= 0)
+    err = np.abs(lam - r.lam).max() / n1
+    assert err <= TOL_LAMBDA, err
+    orth = np.abs(Y.T @ B @ Y - np.eye(M)).max()
+    assert orth <= TOL_ORTH * max(1.0, kappa / 10), (orth, kappa)
+    res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+    assert res <= TOL_RES, res
+    assert max_subspace_sine(Y, r.Y, B, r.lam, 1e-8 * n1) <= 1e-11 * n1 * max(1.0, kappa / 10)
+    lam_c, _ = _gep().solve(to_gpu(A), to_gpu(B))
+    assert np.abs(to_np(lam_c) - lam).max() / n1 <= TOL_LAMBDA
+
+
+def test_solve_cholfree_band64(gpu):
+    """Cholesky-free reducer at band width 64 (ragged order): residual,
+    B-orthogonality, and eigenvalues against the Cholesky path (itself checked
+    against the oracle's Sylvester counts in the band-64 tests above)."""
+    M = 2113
+    say(f"[cholfree] M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 500 + M)
+    lam, Y = _gep().solve_cholfree(to_gpu(A), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    n1 = np.abs(A).sum(axis=0).max()
+    kappa = _cond(B)
+    assert np.abs(Y.T @ B @ Y - np.eye(M)).max() <= TOL_ORTH * max(1.0, kappa / 10)
+    res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+    assert res <= TOL_RES, res
+    lam_c, _ = _gep().solve(to_gpu(A), to_gpu(B))
+    assert np.abs(to_np(lam_c) - lam).max() / n1 <= TOL_LAMBDA
+
+
+def test_solve_cholfree_indefinite_B_reports_info(gpu):
+    """A B with one negative eigenvalue: info = M + 1 (one eigenvalue of B is not
+    positive), raised as LinAlgError."""
+    import torch
+    say("[cholfree] indefinite B")
+    M = 100
+    A, B = synth.banded_pair(M, 5.0, 79)
+    B[40, 40] = -1.0
+    assert int((np.linalg.eigvalsh(B) <= 0).sum()) == 1
+    with pytest.raises(torch.linalg.LinAlgError, match="1 eigenvalues of B"):
+        _gep().solve_cholfree(to_gpu(A), to_gpu(B))
