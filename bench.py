@@ -232,10 +232,12 @@ def lowest_extension(gep, torch, dA, dB, t_full: float, phases_full: dict, lam_f
             "lambda_equal_full": same, "phase_ms": ph}
 
 
-def cholfree_extension(gep, torch, name: str = "m8192", reps: int = 3) -> dict:
-    """Cholesky-free reducer (gep_solve_cholfree: B W = W D by the SEP solver,
-    C = D^-1/2 W^T A W D^-1/2, Y = W D^-1/2 Z) on one of the smaller workloads:
-    median time over `reps` solves after one warm-up, its four phases, the
+def reducer_extension(gep, torch, reducer: str, name: str = "m8192", reps: int = 3) -> dict:
+    """One of the alternative reducers on one of the smaller workloads:
+    "cholfree" (gep_solve_cholfree: B W = W D by the SEP solver,
+    C = D^-1/2 W^T A W D^-1/2, Y = W D^-1/2 Z) or "explicit_inverse"
+    (gep_solve_explicit_inverse: R = L^-1 formed, C = (R A) R^T, Y = R^T Z).
+    Median time over `reps` solves after one warm-up, its four phases, the
     Cholesky path's median time on the same inputs, the eigenvalue difference to
     the Cholesky path, and the residual and B-orthogonality of its result."""
     import numpy as np
@@ -244,36 +246,41 @@ def cholfree_extension(gep, torch, name: str = "m8192", reps: int = 3) -> dict:
     M = A.shape[0]
     dA = torch.from_numpy(A).cuda()
     dB = torch.from_numpy(B).cuda()
-    names = {"R1": "sep_B", "R2-4": "form_C", "S1": "sep_C", "S2": "Y"}
+    if reducer == "cholfree":
+        fn = lambda: gep.solve_cholfree(dA, dB, check_info=False)
+        names = {"R1": "sep_B", "R2-4": "form_C", "S1": "sep_C", "S2": "Y"}
+    else:
+        fn = lambda: gep.solve_explicit_inverse(dA, dB, check_info=False)
+        names = {"R1": "cholesky", "R2-4": "inverse_and_C", "S1": "sep_C", "S2": "Y"}
 
-    def timed(fn):
-        fn()
+    def timed(f):
+        f()
         ts, phases = [], {}
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            out = fn()
+            out = f()
             torch.cuda.synchronize()
             ts.append(time.perf_counter() - t0)
             for k, v in gep.profile_read().items():
                 phases.setdefault(k, []).append(v)
         return sorted(ts)[len(ts) // 2], phases, out
 
-    t_cf, ph_cf, (lam_cf, Y) = timed(lambda: gep.solve_cholfree(dA, dB, check_info=False))
+    t_alt, ph_alt, (lam_alt, Y) = timed(fn)
     t_ch, _, (lam_ch, Yc) = timed(lambda: gep.solve(dA, dB, check_info=False))
     del Yc
     n1 = dA.abs().sum(0).max().item()
     Yc_ = Y.contiguous()
     BY = dB @ Yc_
-    res = ((dA @ Yc_ - BY * lam_cf[None, :]).abs().sum(0).max() / (n1 * Yc_.abs().sum(0).max())).item()
+    res = ((dA @ Yc_ - BY * lam_alt[None, :]).abs().sum(0).max() / (n1 * Yc_.abs().sum(0).max())).item()
     orth = (Yc_.t() @ BY - torch.eye(M, dtype=torch.float64, device=dA.device)).abs().max().item()
-    dlam = ((lam_cf - lam_ch).abs().max() / n1).item()
-    print(f"[bench] cholfree {name}: {t_cf * 1e3:.0f} ms (Cholesky path {t_ch * 1e3:.0f} ms), "
+    dlam = ((lam_alt - lam_ch).abs().max() / n1).item()
+    print(f"[bench] {reducer} {name}: {t_alt * 1e3:.0f} ms (Cholesky path {t_ch * 1e3:.0f} ms), "
           f"|dlambda|/|A|_1 {dlam:.1e}", file=sys.stderr, flush=True)
-    return {"workload": f"{name}_cholfree", "M": M, "solves": reps, "median_ms": t_cf * 1e3,
-            "median_ms_cholesky_path": t_ch * 1e3, "ratio_vs_cholesky_path": t_cf / t_ch,
+    return {"workload": f"{name}_{reducer}", "M": M, "solves": reps, "median_ms": t_alt * 1e3,
+            "median_ms_cholesky_path": t_ch * 1e3, "ratio_vs_cholesky_path": t_alt / t_ch,
             "dlambda_vs_cholesky_path": dlam, "residual": res, "b_orthogonality": orth,
-            "phase_ms": {names[k]: float(np.median(v)) for k, v in ph_cf.items() if k in names}}
+            "phase_ms": {names[k]: float(np.median(v)) for k, v in ph_alt.items() if k in names}}
 
 
 def adjoint_extension(gep, torch) -> dict:
@@ -464,7 +471,9 @@ def main() -> int:
         extensions = {"m32768_lowest_half": lowest,
                       "m512": single_extension(gep, torch, "m512", 5, 50),
                       "m8192": single_extension(gep, torch, "m8192", 1, 5),
-                      "m8192_cholfree": cholfree_extension(gep, torch, "m8192", 3),
+                      "m8192_cholfree": reducer_extension(gep, torch, "cholfree", "m8192", 3),
+                      "m8192_explicit_inverse": reducer_extension(gep, torch, "explicit_inverse",
+                                                                  "m8192", 3),
                       "batched": batched_extension(gep, torch, replays=20),
                       "adjoint": adjoint_extension(gep, torch)}
         torch.cuda.empty_cache()

@@ -132,6 +132,23 @@ int gep_solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B,
                        int32_t* info, void* stream);
 
 /*
+ * Explicit-inverse (ELPA-style) reducer (section 3.1): the Cholesky factorization
+ * B = L L^T as in gep_solve, then the inverse R = L^{-1} formed explicitly (the
+ * paper's R = U^{-1} with U = L^T), the reduced matrix by two successive matrix
+ * products, C = (R A) R^T, and the back transformation as one product,
+ * Y = R^T Z.  About 3 M^3 flops more than gep_solve's reducer, all of them GEMMs.
+ *   A, B, lda, ldb, lambda, Y, ldy, info: as gep_solve with job = GEP_JOB_VECTORS
+ *   (FP64).
+ *   workspace: >= gep_workspace_size_explicit_inverse(M) bytes, 256-byte aligned
+ *   (one M x M buffer more than gep_solve's).
+ * Argument errors name the argument by its position (1 = M ... 11 = info).
+ */
+size_t gep_workspace_size_explicit_inverse(int64_t M);
+int gep_solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const double* B,
+                               int64_t ldb, double* lambda, double* Y, int64_t ldy,
+                               void* workspace, size_t ws_bytes, int32_t* info, void* stream);
+
+/*
  * Many independent problems of different orders in one call (the k-point-like
  * batches of electronic-structure codes; the paper solves one problem per run).
  * Arrays ending in _host are HOST arrays of length `batch` (orders, leading

@@ -51,6 +51,8 @@ SIGNATURES = {
     "gep_solve_lowest": (INT, [I64, P, I64, P, I64, I64, P, P, I64, P, SZ, P, P]),
     "gep_workspace_size_cholfree": (SZ, [I64]),
     "gep_solve_cholfree": (INT, [I64, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
+    "gep_workspace_size_explicit_inverse": (SZ, [I64]),
+    "gep_solve_explicit_inverse": (INT, [I64, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
     "gep_workspace_size_batched": (SZ, [INT, P, INT, INT]),
     "gep_solve_batched": (INT, [INT, P, P, P, P, P, P, P, P, INT, INT, P, SZ, P, P]),
     "gep_reduce_workspace_size": (SZ, [I64]),

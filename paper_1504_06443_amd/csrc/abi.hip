@@ -395,6 +395,69 @@ void solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, in
     for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
 }
 
+// Explicit-inverse (ELPA-style) reducer (section 3.1): after B = L L^T the inverse
+// R = L^{-1} is formed explicitly (the blocked triangular solve applied to the
+// identity; its upper triangle stays exactly zero), the reduced matrix is formed
+// by two successive matrix products, C = (R A) R^T (lower triangle of the second),
+// and the back transformation is one product, Y = R^T Z.  Phase events: 0 start,
+// 1 after the Cholesky factorization, 2 after C is formed, 3 after the SEP of C,
+// 4 .. 10 after Y.
+void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double* lambda, double* Y, int64_t ldy, void* workspace,
+                            size_t ws_bytes, int32_t* info, hipStream_t s, bool prof_on) {
+  fill_i32(info, 1, 0, s);
+  if (M == 0) return;
+  Plan p;
+  Arena a;
+  a.base = (char*)workspace;
+  a.cap = ws_bytes;
+  carve(p, a, M, true);
+  double* R = a.take<double>((size_t)M * M);
+  Prof prof(s);
+  Prof* pp = prof_on ? &prof : nullptr;
+  MathScope fp64(MathMode::Fp64);
+  if (pp) pp->mark(0);
+  // B = L L^T
+  copy_matrix(M, M, B, ldb, p.L, M, s);
+  potrf_rec(p.L, M, M, 0, p.Linv, info, M, p.tmp, s);
+  if (pp) pp->mark(1);
+  // R = L^{-1} I
+  set_matrix(M, M, 0.0, 1.0, R, M, s);
+  trsm_lln(Tri{p.L, M, p.Linv, 0}, M, R, M, M, p.tmp, s);
+  // X = R A (into p.L: L is no longer needed), then C = X R^T, lower triangle
+  symmetrize_from_lower(M, A, lda, p.C, M, s);
+  {
+    Gemm g;
+    g.m = M; g.n = M; g.k = M;
+    g.A = R; g.lda = M; g.B = p.C; g.ldb = M; g.C = p.L; g.ldc = M;
+    gemm(g, s);
+  }
+  {
+    Gemm g;
+    g.transB = true;
+    g.uplo = 1;
+    g.m = M; g.n = M; g.k = M;
+    g.A = p.L; g.lda = M; g.B = R; g.ldb = M; g.C = p.C; g.ldc = M;
+    gemm(g, s);
+  }
+  if (pp) pp->mark(2);
+  // C Z = Z Lambda, Z in p.L
+  sep_vectors(p, lambda, p.L, M, info, s);
+  if (pp) pp->mark(3);
+  // Y = R^T Z
+  {
+    Gemm g;
+    g.transA = true;
+    g.m = M; g.n = M; g.k = M;
+    g.A = R; g.lda = M; g.B = p.L; g.ldb = M; g.C = Y; g.ldc = ldy;
+    gemm(g, s);
+  }
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
+  GEP_LAUNCH_CHECK();
+  if (pp)
+    for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
+}
+
 // ---------------------------------------------------------------- batches
 // Instances run on NSTREAM worker streams forked from the caller's stream with
 // events (so the whole batch can be captured in one graph).  Longest-processing-
@@ -601,6 +664,39 @@ int gep_solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B,
   hipStream_t s = (hipStream_t)stream;
   return guarded([&]() -> int {
     solve_cholfree(M, A, lda, B, ldb, lambda, Y, ldy, workspace, ws_bytes, info, s, true);
+    return GEP_OK;
+  });
+}
+
+size_t gep_workspace_size_explicit_inverse(int64_t M) {
+  if (M <= 0) return 256;
+  Plan p;
+  Arena a;
+  a.dry = true;
+  carve(p, a, M, true);
+  a.take<double>((size_t)M * M);
+  return a.used + 256;
+}
+
+int gep_solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const double* B,
+                               int64_t ldb, double* lambda, double* Y, int64_t ldy,
+                               void* workspace, size_t ws_bytes, int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (M > 0 && !lambda) return bad(6);
+  if (M > 0 && !Y) return bad(7);
+  if (ldy < m1) return bad(8);
+  if (!info) return bad(11);
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(9);
+  if (ws_bytes < gep_workspace_size_explicit_inverse(M)) return GEP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    solve_explicit_inverse(M, A, lda, B, ldb, lambda, Y, ldy, workspace, ws_bytes, info, s, true);
     return GEP_OK;
   });
 }

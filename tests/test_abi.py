@@ -191,3 +191,37 @@ def test_solve_cholfree_workspace(lib):
     assert lib.gep_workspace_size_cholfree(0) == 256
     need = lib.gep_workspace_size_cholfree(M)
     assert _cholfree(lib, M, wsb=need - 1) == -2
+
+
+def _explicit(lib, M, lda=None, A=FAKE, B=FAKE, lam=FAKE, Y=FAKE, ldy=None, ws=P(0x200000),
+              wsb=None, info=FAKE):
+    lda = M if lda is None else lda
+    ldy = max(M, 1) if ldy is None else ldy
+    wsb = lib.gep_workspace_size_explicit_inverse(max(M, 0)) if wsb is None else wsb
+    return lib.gep_solve_explicit_inverse(M, A, lda, B, max(M, 1), lam, Y, ldy, ws, wsb, info,
+                                          None)
+
+
+@pytest.mark.parametrize("kwargs,arg", [
+    (dict(M=-1), 1),
+    (dict(M=10, A=P(0)), 2),
+    (dict(M=10, lda=9), 3),
+    (dict(M=10, B=P(0)), 4),
+    (dict(M=10, lam=P(0)), 6),
+    (dict(M=10, Y=P(0)), 7),
+    (dict(M=10, ldy=9), 8),
+    (dict(M=10, ws=P(0x200010)), 9),
+    (dict(M=10, info=P(0)), 11),
+])
+def test_solve_explicit_inverse_rejects_bad_arguments(lib, kwargs, arg):
+    assert _explicit(lib, **kwargs) == -1
+    assert lib.gep_last_bad_arg() == arg
+
+
+def test_solve_explicit_inverse_workspace(lib):
+    M = 300
+    # one M x M buffer (R = L^-1) on top of gep_solve's needs
+    assert lib.gep_workspace_size_explicit_inverse(M) >= lib.gep_workspace_size(M, 1, 0) + 8 * M * M
+    assert lib.gep_workspace_size_explicit_inverse(0) == 256
+    need = lib.gep_workspace_size_explicit_inverse(M)
+    assert _explicit(lib, M, wsb=need - 1) == -2

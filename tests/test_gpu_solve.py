@@ -219,3 +219,47 @@ def test_solve_cholfree_indefinite_B_reports_info(gpu):
     assert int((np.linalg.eigvalsh(B) <= 0).sum()) == 1
     with pytest.raises(torch.linalg.LinAlgError, match="1 eigenvalues of B"):
         _gep().solve_cholfree(to_gpu(A), to_gpu(B))
+
+
+
+@pytest.mark.parametrize("M", [1, 2, 17, 64, 129, 300, 700])
+def test_solve_explicit_inverse_matches_oracle(gpu, M):
+    """Explicit-inverse (ELPA-style) reducer (R = L^-1 formed, C = (R A) R^T,
+    Y = R^T Z) against the oracle, with the same bounds as the Cholesky path, and
+    its eigenvalues against the Cholesky path's."""
+    say(f"[explicit inverse] M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 800 + M)
+    lam, Y = _gep().solve_explicit_inverse(to_gpu(A), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    r = oracle.solve(A, B)
+    check_against_oracle(A, B, lam, Y, r)
+    lam_c, _ = _gep().solve(to_gpu(A), to_gpu(B))
+    assert np.abs(to_np(lam_c) - lam).max() / r.norm1 <= TOL_LAMBDA
+
+
+def test_solve_explicit_inverse_band64(gpu):
+    """Explicit-inverse reducer at band width 64 (ragged order, several 128-row
+    diagonal blocks of L^-1): residual, B-orthogonality, eigenvalues against the
+    Cholesky path."""
+    M = 2113
+    say(f"[explicit inverse] M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 500 + M)
+    lam, Y = _gep().solve_explicit_inverse(to_gpu(A), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    n1 = np.abs(A).sum(axis=0).max()
+    assert np.abs(Y.T @ B @ Y - np.eye(M)).max() <= TOL_ORTH
+    res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+    assert res <= TOL_RES, res
+    lam_c, _ = _gep().solve(to_gpu(A), to_gpu(B))
+    assert np.abs(to_np(lam_c) - lam).max() / n1 <= TOL_LAMBDA
+
+
+def test_solve_explicit_inverse_indefinite_B_reports_info(gpu):
+    """Cholesky breakdown at the leading minor of order 41: info = M + 41."""
+    import torch
+    say("[explicit inverse] indefinite B")
+    M = 100
+    A, B = synth.banded_pair(M, 5.0, 79)
+    B[40, 40] = -1.0
+    with pytest.raises(torch.linalg.LinAlgError, match="order 41"):
+        _gep().solve_explicit_inverse(to_gpu(A), to_gpu(B))
