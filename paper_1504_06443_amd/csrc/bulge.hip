@@ -53,13 +53,6 @@ __device__ inline void cst(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Sum over groups of 4 consecutive lanes.
-__device__ inline double quad_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
-  return v;
-}
-
 // Householder for x (length L, in LDS): H x = beta e_1, H = I - tau v v^T,
 // v[0] = 1.  Overwrites x by v.  Wave 0 reduces; all threads return beta, tau.
 __device__ void house(int L, double* x, double* sh, double& beta_out, double& tau_out) {
@@ -91,23 +84,27 @@ __device__ void house(int L, double* x, double* sh, double& beta_out, double& ta
   __syncthreads();
 }
 
-// Every loop over a block column or row below has a fixed trip count of
-// PER = MAXB / 4: each thread first reads all of its (up to PER) operands from
-// LDS, with indices past the end clamped to a valid element, and only then
-// computes and writes, so the reads' latencies overlap instead of adding up.
-constexpr int PER = MAXB / (NT / 64);
+// The bulge chase runs CNT threads per workgroup: CW waves, two per SIMD, so
+// that the latency of one wave's dependent LDS and ALU steps is partly covered by
+// the other's.  Every loop over a block column or row below has a fixed trip
+// count of PER = MAXB / CW: each thread first reads all of its (up to PER)
+// operands from LDS, with indices past the end clamped to a valid element, and
+// only then computes and writes, so the reads' latencies overlap.
+constexpr int CNT = 512;
+constexpr int CW = CNT / 64;
+constexpr int PER = MAXB / CW;
 
-// out[x] = scale * sum_{y < ny} M[x * sx + y * sy] w[y] for x < nx: four threads
-// per x, each summing y = q, q + 4, ... pairwise; the four partials are added
-// in a fixed order.
-__device__ inline void matvec4(int nx, int ny, const double* M, int sx, int sy, const double* w,
-                               double scale, double* out) {
-  const int tid = threadIdx.x, x = tid >> 2, q = tid & 3;
+// out[x] = scale * sum_{y < ny} M[x * sx + y * sy] w[y] for x < nx: CW threads
+// per x, each summing y = q, q + CW, ... pairwise; the CW partials are added in a
+// fixed order.
+__device__ inline void matvec(int nx, int ny, const double* M, int sx, int sy, const double* w,
+                              double scale, double* out) {
+  const int tid = threadIdx.x, x = tid / CW, q = tid % CW;
   const int xc = x < nx ? x : 0;
   double t[PER];
 #pragma unroll
   for (int m = 0; m < PER; ++m) {
-    const int y = q + 4 * m;
+    const int y = q + CW * m;
     const int yc = y < ny ? y : 0;
     const double prod = M[xc * sx + yc * sy] * w[yc];
     t[m] = y < ny ? prod : 0.0;
@@ -116,7 +113,9 @@ __device__ inline void matvec4(int nx, int ny, const double* M, int sx, int sy, 
   for (int h = PER / 2; h >= 1; h >>= 1)
 #pragma unroll
     for (int m = 0; m < h; ++m) t[m] += t[m + h];
-  const double acc = quad_sum(t[0]);
+  double acc = t[0];
+#pragma unroll
+  for (int o = 1; o < CW; o <<= 1) acc += __shfl_xor(acc, o, 64);
   if (x < nx && q == 0) out[x] = scale * acc;
 }
 
@@ -125,7 +124,7 @@ __device__ inline void matvec4(int nx, int ny, const double* M, int sx, int sy, 
 __device__ void two_sided(int L, double* D, const double* v, double tau, double* p, double* sh) {
   const int tid = threadIdx.x;
   if (tau == 0.0) return;
-  matvec4(L, L, D, 1, LDS_LD, v, tau, p);
+  matvec(L, L, D, 1, LDS_LD, v, tau, p);
   __syncthreads();
   if (tid < 64) {
     double s = 0.0;
@@ -142,7 +141,7 @@ __device__ void two_sided(int L, double* D, const double* v, double tau, double*
       double d[PER], pv[PER], vv[PER];
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
-        const int j = j0 + 4 * m;
+        const int j = j0 + CW * m;
         const int jc = j < L ? j : 0;
         d[m] = D[i + jc * LDS_LD];
         pv[m] = p[jc];
@@ -150,7 +149,7 @@ __device__ void two_sided(int L, double* D, const double* v, double tau, double*
       }
 #pragma unroll
       for (int m = 0; m < PER; ++m) {
-        const int j = j0 + 4 * m;
+        const int j = j0 + CW * m;
         const double pj = pv[m] - a * vv[m];
         if (j < L) D[i + j * LDS_LD] = d[m] - (vi * pj + pi * vv[m]);
       }
@@ -199,7 +198,7 @@ __device__ bool wait_for(const ChaseArgs& a, int64_t s, int32_t need) {
   }
 }
 
-__global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
+__global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
   __shared__ double Es[MAXB * LDS_LD];
   __shared__ double Ds[MAXB * LDS_LD];
   __shared__ double v[MAXB], vprev[MAXB], p[MAXB];
@@ -247,14 +246,14 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
         double xd[PER], xe[PER];
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
-          const int j = j0 + (NT / 64) * m;
+          const int j = j0 + CW * m;
           const bool okd = i < L && j <= i;
           xd[m] = cld(&band[okd ? (i - j) + (r + j) * ld : 0]);
         }
         if (k > 0) {
 #pragma unroll
           for (int m = 0; m < PER; ++m) {
-            const int j = j0 + (NT / 64) * m;
+            const int j = j0 + CW * m;
             const bool oke = i < L && j < Lprev;
             xe[m] = cld(&band[oke ? (b + i - j) + (c + j) * ld : 0]);
           }
@@ -263,7 +262,7 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
         if (k == 0 && tid < L) xv = cld(&band[(1 + tid) + s * ld]);
 #pragma unroll
         for (int m = 0; m < PER; ++m) {
-          const int j = j0 + (NT / 64) * m;
+          const int j = j0 + CW * m;
           if (i < L && j <= i) {
             Ds[i + j * LDS_LD] = xd[m];
             Ds[j + i * LDS_LD] = xd[m];
@@ -272,7 +271,7 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
         if (k > 0) {
 #pragma unroll
           for (int m = 0; m < PER; ++m) {
-            const int j = j0 + (NT / 64) * m;
+            const int j = j0 + CW * m;
             if (i < L && j < Lprev) Es[i + j * LDS_LD] = xe[m];
           }
         }
@@ -285,7 +284,7 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
       } else {
         // E <- E (I - tau_prev vprev vprev^T)
         if (tau_prev != 0.0) {
-          matvec4(L, Lprev, Es, 1, LDS_LD, vprev, tau_prev, p);
+          matvec(L, Lprev, Es, 1, LDS_LD, vprev, tau_prev, p);
           __syncthreads();
           {
             const int i = tid & 63, j0 = tid >> 6;
@@ -294,14 +293,14 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
               double e[PER], vv[PER];
 #pragma unroll
               for (int m = 0; m < PER; ++m) {
-                const int j = j0 + 4 * m;
+                const int j = j0 + CW * m;
                 const int jc = j < Lprev ? j : 0;
                 e[m] = Es[i + jc * LDS_LD];
                 vv[m] = vprev[jc];
               }
 #pragma unroll
               for (int m = 0; m < PER; ++m) {
-                const int j = j0 + 4 * m;
+                const int j = j0 + CW * m;
                 if (j < Lprev) Es[i + j * LDS_LD] = e[m] - pi * vv[m];
               }
             }
@@ -314,7 +313,7 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
         house(L, v, sh, beta, tau);
         if (tau != 0.0) {
           // p[col] = tau v^T E(:, col); column 0 is replaced by beta e_1 below
-          matvec4(Lprev, L, Es, LDS_LD, 1, v, tau, p);
+          matvec(Lprev, L, Es, LDS_LD, 1, v, tau, p);
           __syncthreads();
           {
             const int i = tid & 63, j0 = tid >> 6;
@@ -323,14 +322,14 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
               double e[PER], pp[PER];
 #pragma unroll
               for (int m = 0; m < PER; ++m) {
-                const int j = j0 + 4 * m;
+                const int j = j0 + CW * m;
                 const int jc = j < Lprev ? j : 0;
                 e[m] = Es[i + jc * LDS_LD];
                 pp[m] = p[jc];
               }
 #pragma unroll
               for (int m = 0; m < PER; ++m) {
-                const int j = j0 + 4 * m;
+                const int j = j0 + CW * m;
                 if (j >= 1 && j < Lprev) Es[i + j * LDS_LD] = e[m] - vi * pp[m];
               }
             }
@@ -354,12 +353,12 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
           double e[PER];
 #pragma unroll
           for (int m = 0; m < PER; ++m) {
-            const int j = j0 + 4 * m;
+            const int j = j0 + CW * m;
             e[m] = Es[i + (j < Lprev ? j : 0) * LDS_LD];
           }
 #pragma unroll
           for (int m = 0; m < PER; ++m) {
-            const int j = j0 + 4 * m;
+            const int j = j0 + CW * m;
             if (j < Lprev) cst(&band[(b + i - j) + (c + j) * ld], e[m]);
           }
         }
@@ -371,12 +370,12 @@ __global__ void __launch_bounds__(NT) chase_kernel(ChaseArgs a) {
             double d[PER];
 #pragma unroll
             for (int m = 0; m < PER; ++m) {
-              const int j = j0 + 4 * m;
+              const int j = j0 + CW * m;
               d[m] = Ds[i + (j <= i ? j : 0) * LDS_LD];
             }
 #pragma unroll
             for (int m = 0; m < PER; ++m) {
-              const int j = j0 + 4 * m;
+              const int j = j0 + CW * m;
               if (j <= i) cst(&band[(i - j) + (r + j) * ld], d[m]);
             }
           }
@@ -1015,7 +1014,7 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     if (groups > nsweeps) groups = nsweeps;
     if (groups > 512) groups = 512;
     ProbeScope probe(PROBE_CHASE, s, 6.0 * c.b * (double)n * (double)n);
-    hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(NT), 0, s, a);
+    hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(CNT), 0, s, a);
     GEP_LAUNCH_CHECK();
   }
   hipLaunchKernelGGL(extract_tridiag, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n,
