@@ -395,11 +395,47 @@ void solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, in
     for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
 }
 
+// X = op(R) A, out of place, for a lower-triangular R (n x n, leading dimension
+// ldr, upper triangle zero): op(R) = R, or R^T when trans.  A and X are n x ncols.
+// Recursive halving at a multiple of NB; M^3 flops for n = ncols = M instead of a
+// full GEMM's 2 M^3.
+void trmm_lower(bool trans, int64_t n, const double* R, int64_t ldr, const double* A,
+                int64_t lda, double* X, int64_t ldx, int64_t ncols, hipStream_t s) {
+  if (n <= 0 || ncols <= 0) return;
+  if (n <= NB) {
+    Gemm g;
+    g.transA = trans;
+    g.m = n; g.n = ncols; g.k = n;
+    g.A = R; g.lda = ldr; g.B = A; g.ldb = lda; g.C = X; g.ldc = ldx;
+    gemm(g, s);
+    return;
+  }
+  const int64_t n1 = NB * ((cdiv(n, NB) + 1) / 2), n2 = n - n1;
+  const double* R21 = R + n1;               // n2 x n1
+  const double* R22 = R + n1 + n1 * ldr;    // n2 x n2
+  trmm_lower(trans, n1, R, ldr, A, lda, X, ldx, ncols, s);
+  trmm_lower(trans, n2, R22, ldr, A + n1, lda, X + n1, ldx, ncols, s);
+  Gemm g;
+  g.beta = 1.0;
+  g.n = ncols;
+  g.A = R21; g.lda = ldr; g.ldb = lda; g.ldc = ldx;
+  if (!trans) {  // X2 += R21 A1
+    g.m = n2; g.k = n1;
+    g.B = A; g.C = X + n1;
+  } else {       // X1 += R21^T A2
+    g.transA = true;
+    g.m = n1; g.k = n2;
+    g.B = A + n1; g.C = X;
+  }
+  gemm(g, s);
+}
+
 // Explicit-inverse (ELPA-style) reducer (section 3.1): after B = L L^T the inverse
 // R = L^{-1} is formed explicitly (the blocked triangular solve applied to the
 // identity; its upper triangle stays exactly zero), the reduced matrix is formed
-// by two successive matrix products, C = (R A) R^T (lower triangle of the second),
-// and the back transformation is one product, Y = R^T Z.  Phase events: 0 start,
+// by two successive matrix products, C = (R A) R^T (a triangular multiply, then the
+// lower triangle of a GEMM), and the back transformation is one triangular
+// multiply, Y = R^T Z.  Phase events: 0 start,
 // 1 after the Cholesky factorization, 2 after C is formed, 3 after the SEP of C,
 // 4 .. 10 after Y.
 void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const double* B,
@@ -426,12 +462,7 @@ void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const doubl
   trsm_lln(Tri{p.L, M, p.Linv, 0}, M, R, M, M, p.tmp, s);
   // X = R A (into p.L: L is no longer needed), then C = X R^T, lower triangle
   symmetrize_from_lower(M, A, lda, p.C, M, s);
-  {
-    Gemm g;
-    g.m = M; g.n = M; g.k = M;
-    g.A = R; g.lda = M; g.B = p.C; g.ldb = M; g.C = p.L; g.ldc = M;
-    gemm(g, s);
-  }
+  trmm_lower(false, M, R, M, p.C, M, p.L, M, M, s);
   {
     Gemm g;
     g.transB = true;
@@ -445,13 +476,7 @@ void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const doubl
   sep_vectors(p, lambda, p.L, M, info, s);
   if (pp) pp->mark(3);
   // Y = R^T Z
-  {
-    Gemm g;
-    g.transA = true;
-    g.m = M; g.n = M; g.k = M;
-    g.A = R; g.lda = M; g.B = p.L; g.ldb = M; g.C = Y; g.ldc = ldy;
-    gemm(g, s);
-  }
+  trmm_lower(true, M, R, M, p.L, M, Y, ldy, M, s);
   hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
   GEP_LAUNCH_CHECK();
   if (pp)
