@@ -134,9 +134,11 @@ int gep_solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B,
 /*
  * Explicit-inverse (ELPA-style) reducer (section 3.1): the Cholesky factorization
  * B = L L^T as in gep_solve, then the inverse R = L^{-1} formed explicitly (the
- * paper's R = U^{-1} with U = L^T), the reduced matrix by two successive matrix
- * products, C = (R A) R^T, and the back transformation as one product,
- * Y = R^T Z.  About 3 M^3 flops more than gep_solve's reducer, all of them GEMMs.
+ * paper's R = U^{-1} with U = L^T; recursive, from the Cholesky's inverted
+ * diagonal blocks, M^3/3 flops), the reduced matrix by two successive matrix
+ * products, C = (R A) R^T (a triangular multiply and the lower triangle of a
+ * GEMM, 2 M^3), and the back transformation as one triangular multiply,
+ * Y = R^T Z (M^3).  All of it runs as GEMMs on the matrix cores.
  *   A, B, lda, ldb, lambda, Y, ldy, info: as gep_solve with job = GEP_JOB_VECTORS
  *   (FP64).
  *   workspace: >= gep_workspace_size_explicit_inverse(M) bytes, 256-byte aligned

@@ -395,16 +395,18 @@ void solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, in
     for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
 }
 
-// X = op(R) A, out of place, for a lower-triangular R (n x n, leading dimension
-// ldr, upper triangle zero): op(R) = R, or R^T when trans.  A and X are n x ncols.
-// Recursive halving at a multiple of NB; M^3 flops for n = ncols = M instead of a
-// full GEMM's 2 M^3.
+// X = alpha op(R) A, out of place, for a lower-triangular R (n x n, leading
+// dimension ldr, upper triangle zero): op(R) = R, or R^T when trans.  A and X are
+// n x ncols.  Recursive halving at a multiple of NB; M^3 flops for n = ncols = M
+// instead of a full GEMM's 2 M^3.
 void trmm_lower(bool trans, int64_t n, const double* R, int64_t ldr, const double* A,
-                int64_t lda, double* X, int64_t ldx, int64_t ncols, hipStream_t s) {
+                int64_t lda, double* X, int64_t ldx, int64_t ncols, hipStream_t s,
+                double alpha = 1.0) {
   if (n <= 0 || ncols <= 0) return;
   if (n <= NB) {
     Gemm g;
     g.transA = trans;
+    g.alpha = alpha;
     g.m = n; g.n = ncols; g.k = n;
     g.A = R; g.lda = ldr; g.B = A; g.ldb = lda; g.C = X; g.ldc = ldx;
     gemm(g, s);
@@ -413,9 +415,10 @@ void trmm_lower(bool trans, int64_t n, const double* R, int64_t ldr, const doubl
   const int64_t n1 = NB * ((cdiv(n, NB) + 1) / 2), n2 = n - n1;
   const double* R21 = R + n1;               // n2 x n1
   const double* R22 = R + n1 + n1 * ldr;    // n2 x n2
-  trmm_lower(trans, n1, R, ldr, A, lda, X, ldx, ncols, s);
-  trmm_lower(trans, n2, R22, ldr, A + n1, lda, X + n1, ldx, ncols, s);
+  trmm_lower(trans, n1, R, ldr, A, lda, X, ldx, ncols, s, alpha);
+  trmm_lower(trans, n2, R22, ldr, A + n1, lda, X + n1, ldx, ncols, s, alpha);
   Gemm g;
+  g.alpha = alpha;
   g.beta = 1.0;
   g.n = ncols;
   g.A = R21; g.lda = ldr; g.ldb = lda; g.ldc = ldx;
@@ -430,9 +433,51 @@ void trmm_lower(bool trans, int64_t n, const double* R, int64_t ldr, const doubl
   gemm(g, s);
 }
 
+// X = A R, out of place, for a lower-triangular R (n x n, upper triangle zero) and
+// A, X of m x n: [X1 X2] = [A1 R11 + A2 R21, A2 R22].
+void trmm_right_lower(int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
+                      int64_t ldr, double* X, int64_t ldx, hipStream_t s) {
+  if (m <= 0 || n <= 0) return;
+  if (n <= NB) {
+    Gemm g;
+    g.m = m; g.n = n; g.k = n;
+    g.A = A; g.lda = lda; g.B = R; g.ldb = ldr; g.C = X; g.ldc = ldx;
+    gemm(g, s);
+    return;
+  }
+  const int64_t n1 = NB * ((cdiv(n, NB) + 1) / 2), n2 = n - n1;
+  trmm_right_lower(m, n1, A, lda, R, ldr, X, ldx, s);
+  trmm_right_lower(m, n2, A + n1 * lda, lda, R + n1 + n1 * ldr, ldr, X + n1 * ldx, ldx, s);
+  Gemm g;  // X1 += A2 R21
+  g.beta = 1.0;
+  g.m = m; g.n = n1; g.k = n2;
+  g.A = A + n1 * lda; g.lda = lda; g.B = R + n1; g.ldb = ldr; g.C = X; g.ldc = ldx;
+  gemm(g, s);
+}
+
+// R = L^{-1} for the Cholesky factor's diagonal block at global offset `off` (a
+// multiple of NB) of order n: the NB x NB leaves are the inverses the Cholesky
+// already formed (Linv), and above them R21 = -R22 (L21 R11), two triangular
+// multiplies; M^3 / 3 flops in all.  R's upper triangle must be zero on entry;
+// T is scratch for the n/2 x n/2 product (leading dimension ldt).
+void trtri_lower(int64_t n, const double* L, int64_t ldl, const double* Linv, int64_t off,
+                 double* R, int64_t ldr, double* T, int64_t ldt, hipStream_t s) {
+  if (n <= 0) return;
+  if (n <= NB) {
+    copy_matrix(n, n, Linv + (off / NB) * (int64_t)NB * NB, NB, R, ldr, s);
+    return;
+  }
+  const int64_t n1 = NB * ((cdiv(n, NB) + 1) / 2), n2 = n - n1;
+  trtri_lower(n1, L, ldl, Linv, off, R, ldr, T, ldt, s);
+  trtri_lower(n2, L + n1 + n1 * ldl, ldl, Linv, off + n1, R + n1 + n1 * ldr, ldr, T, ldt, s);
+  trmm_right_lower(n2, n1, L + n1, ldl, R, ldr, T, ldt, s);                   // T = L21 R11
+  trmm_lower(false, n2, R + n1 + n1 * ldr, ldr, T, ldt, R + n1, ldr, n1, s, -1.0);  // R21
+}
+
 // Explicit-inverse (ELPA-style) reducer (section 3.1): after B = L L^T the inverse
-// R = L^{-1} is formed explicitly (the blocked triangular solve applied to the
-// identity; its upper triangle stays exactly zero), the reduced matrix is formed
+// R = L^{-1} is formed explicitly (recursive triangular inversion from the
+// Cholesky's inverted diagonal blocks; its upper triangle is zero), the reduced
+// matrix is formed
 // by two successive matrix products, C = (R A) R^T (a triangular multiply, then the
 // lower triangle of a GEMM), and the back transformation is one triangular
 // multiply, Y = R^T Z.  Phase events: 0 start,
@@ -457,9 +502,9 @@ void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const doubl
   copy_matrix(M, M, B, ldb, p.L, M, s);
   potrf_rec(p.L, M, M, 0, p.Linv, info, M, p.tmp, s);
   if (pp) pp->mark(1);
-  // R = L^{-1} I
-  set_matrix(M, M, 0.0, 1.0, R, M, s);
-  trsm_lln(Tri{p.L, M, p.Linv, 0}, M, R, M, M, p.tmp, s);
+  // R = L^{-1} (p.C is the scratch of the recursion)
+  set_matrix(M, M, 0.0, 0.0, R, M, s);
+  trtri_lower(M, p.L, M, p.Linv, 0, R, M, p.C, M, s);
   // X = R A (into p.L: L is no longer needed), then C = X R^T, lower triangle
   symmetrize_from_lower(M, A, lda, p.C, M, s);
   trmm_lower(false, M, R, M, p.C, M, p.L, M, M, s);
