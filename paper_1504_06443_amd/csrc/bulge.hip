@@ -119,21 +119,41 @@ __device__ inline void matvec(int nx, int ny, const double* M, int sx, int sy, c
   if (x < nx && q == 0) out[x] = scale * acc;
 }
 
+// Householder for x (length L <= 64, in LDS, not modified): H x = beta e_1,
+// H = I - tau v v^T, v[0] = 1, written to vout.  Every wave forms the squared norm
+// with the same butterfly (so every lane holds the same bits) and every thread
+// the same scalars, so no barrier is needed before vout is written; one after.
+__device__ void house_from(int L, const double* x, double* vout, double& beta_out,
+                           double& tau_out) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  double s = (lane >= 1 && lane < L) ? x[lane] * x[lane] : 0.0;
+  s = wave_sum(s);
+  const double x0 = x[0];
+  double beta, tau, scal;
+  if (s == 0.0 || L <= 1) {
+    beta = x0; tau = 0.0; scal = 0.0;
+  } else {
+    const double mu = sqrt(x0 * x0 + s);
+    beta = (x0 >= 0.0) ? -mu : mu;
+    tau = (beta - x0) / beta;
+    scal = 1.0 / (x0 - beta);
+  }
+  if (tid < L) vout[tid] = (tid == 0) ? 1.0 : x[tid] * scal;
+  beta_out = beta;
+  tau_out = tau;
+  __syncthreads();
+}
+
 // D (L x L symmetric, full in LDS, ld LDS_LD) <- H D H, H = I - tau v v^T.
 // 4 threads per row for the matrix-vector product.
-__device__ void two_sided(int L, double* D, const double* v, double tau, double* p, double* sh) {
+__device__ void two_sided(int L, double* D, const double* v, double tau, double* p) {
   const int tid = threadIdx.x;
   if (tau == 0.0) return;
   matvec(L, L, D, 1, LDS_LD, v, tau, p);
   __syncthreads();
-  if (tid < 64) {
-    double s = 0.0;
-    for (int i = tid; i < L; i += 64) s += p[i] * v[i];
-    s = wave_sum(s);
-    if (tid == 0) sh[3] = 0.5 * tau * s;
-  }
-  __syncthreads();
-  const double a = sh[3];
+  // a = tau p^T v / 2, formed by every wave (identical bits on every lane)
+  const int lane = tid & 63;
+  const double a = 0.5 * tau * wave_sum(lane < L ? p[lane] * v[lane] : 0.0);
   {
     const int i = tid & 63, j0 = tid >> 6;
     if (i < L) {
@@ -307,10 +327,9 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
           }
           __syncthreads();
         }
-        // reflector from column 0 of E, applied from the left to columns 1..
-        if (tid < L) v[tid] = Es[tid];
-        __syncthreads();
-        house(L, v, sh, beta, tau);
+        // reflector from column 0 of E (read in place), applied from the left to
+        // columns 1..
+        house_from(L, Es, v, beta, tau);
         if (tau != 0.0) {
           // p[col] = tau v^T E(:, col); column 0 is replaced by beta e_1 below
           matvec(Lprev, L, Es, LDS_LD, 1, v, tau, p);
@@ -343,7 +362,7 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
       // all issued after its arithmetic: the wait for a load's data also waits for
       // every store issued before that load, and the release below has to wait
       // for the stores anyway.
-      if (tau != 0.0) two_sided(L, Ds, v, tau, p, sh);
+      if (tau != 0.0) two_sided(L, Ds, v, tau, p);
       if (k == 0) {
         if (tid == 0) cst(&band[1 + s * ld], beta);
         if (tid >= 1 && tid < L) cst(&band[(1 + tid) + s * ld], 0.0);
