@@ -1,6 +1,6 @@
 """Pins for the CPU oracle: closed forms, brute force, invariants and an
 independent library, so that the oracle is checked against something other than
-itself before it is used to judge the GPU library."""
+itself before it serves as the reference for the GPU library."""
 from fractions import Fraction
 
 import mpmath
