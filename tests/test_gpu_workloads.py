@@ -79,3 +79,49 @@ def test_workload_against_stored_oracle(gpu, name, prec):
     assert err <= TOL_LAMBDA
     assert res <= BARS[prec][0]
     assert orth <= BARS[prec][1]
+
+
+@pytest.mark.parametrize("reducer", ["explicit_inverse", "cholfree"])
+def test_workload_alternative_reducers(gpu, reducer):
+    """The two alternative reducers on the 8192 workload: every eigenvalue against
+    the stored oracle eigenvalues, the oracle's counts below the fixed shifts, and
+    the full-size invariants (the Cholesky-free path's B-orthogonality bound is
+    scaled by cond(B)/10, as in the small-size tests)."""
+    import torch
+    import paper_1504_06443_amd as gep
+    name = "m8192"
+    ref, inertia = _stored(name)
+    if ref is None:
+        pytest.skip(f"no stored oracle eigenvalues for {name}")
+    A, B = synth.workload(name)
+    w = np.linalg.eigvalsh(B) if reducer == "cholfree" else None
+    kappa = float(w[-1] / w[0]) if w is not None else 1.0
+    dA = torch.from_numpy(A).to("cuda:0")
+    dB = torch.from_numpy(B).to("cuda:0")
+    del A, B
+    n1 = dA.abs().sum(0).max().item()
+    say(f"[workload] {name} {reducer}: solving")
+    fn = gep.solve_explicit_inverse if reducer == "explicit_inverse" else gep.solve_cholfree
+    lam, Y = fn(dA, dB)
+    torch.cuda.synchronize()
+    lam_h = lam.cpu().numpy()
+    err = np.abs(lam_h - ref).max() / n1
+    for sigma, count in (inertia or {}).items():
+        assert int(np.sum(lam_h < float(sigma))) == count, (sigma, count)
+    with torch.no_grad():
+        Yc = Y.contiguous()
+        del Y
+        BY = dB @ Yc
+        R = dA @ Yc
+        R -= BY * lam[None, :]
+        res = (R.abs().sum(0).max() / (n1 * Yc.abs().sum(0).max())).item()
+        del R
+        G = Yc.t() @ BY
+        G.diagonal().sub_(1.0)
+        orth = G.abs().max().item()
+        del G, BY, Yc
+    torch.cuda.empty_cache()
+    say(f"  |dlambda|/|A|_1 {err:.2e}, residual {res:.2e}, B-orthogonality {orth:.2e}")
+    assert err <= TOL_LAMBDA
+    assert res <= BARS["fp64"][0]
+    assert orth <= BARS["fp64"][1] * max(1.0, kappa / 10)
