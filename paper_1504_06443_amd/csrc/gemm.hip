@@ -717,7 +717,7 @@ int choose_split(int64_t m, int64_t n, int64_t k) {
 // launch has about 1024 workgroups, limited by the scratch the caller passes.
 int choose_split_sym(int64_t m, int64_t n, int64_t k, size_t work_elems) {
   const int64_t tiles = cdiv(m, 64) * cdiv(n, 64);
-  int64_t sp = cdiv(1024, tiles);
+  int64_t sp = cdiv(2048, tiles);
   const int64_t by_k = k / KCHUNK_MIN;
   if (sp > by_k) sp = by_k;
   const int64_t by_work = (int64_t)(work_elems / ((size_t)m * (size_t)n));
