@@ -322,7 +322,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--size", type=int, default=32768)
-    ap.add_argument("--cpu-sample", type=int, default=1536)
+    ap.add_argument("--cpu-sample", type=int, default=2560)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
