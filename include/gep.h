@@ -32,7 +32,16 @@
  *   - numerical failures are reported asynchronously in the device int32 `info`
  *     (LAPACK generalized-driver convention): 0 = success; k in [1, M] = the
  *     tridiagonal eigensolver did not converge for eigenvalue k; M + k = the
- *     leading minor of order k of B is not positive definite.
+ *     leading minor of order k of B is not positive definite.  Two device-side
+ *     failures that LAPACK does not have use negative codes (argument errors
+ *     never reach info: they return synchronously):
+ *       GEP_INFO_WAIT_TIMEOUT (-1): a bounded wait between workgroups gave up
+ *         (the full -> band reduction's grid barrier or the bulge chase's hand-off
+ *         between sweeps waited longer than 10 s); the remaining panels or sweeps
+ *         were skipped and lambda / Y are not valid;
+ *       GEP_INFO_REFINE_FAILED (-2): GEP_PREC_MIXED only, a block of Y^T B Y in
+ *         the FP64 refinement was not positive definite; lambda / Y not valid.
+ *     The first failure recorded wins; later ones do not overwrite it.
  *   - M = 0 is a no-op.
  *
  * Eigenvalues are returned in ascending order; for each eigenvector the entry of
@@ -56,6 +65,10 @@ typedef enum {
   GEP_ERR_NO_DEVICE = -4,  /* no usable gfx950 device */
   GEP_ERR_INTERNAL = -5
 } gep_status;
+
+/* Negative device info codes (see the conventions above). */
+#define GEP_INFO_WAIT_TIMEOUT (-1)
+#define GEP_INFO_REFINE_FAILED (-2)
 
 typedef enum { GEP_JOB_VALUES = 0, GEP_JOB_VECTORS = 1 } gep_job;
 typedef enum { GEP_PREC_FP64 = 0, GEP_PREC_MIXED = 1 } gep_prec;
@@ -272,6 +285,25 @@ int gep_profile_read(double* ms, int n);
 int gep_probe_enable(int on);
 int gep_probe_read(int kernel, int64_t* launches, double* ms, double* flops);
 const char* gep_probe_name(int kernel);
+
+/*
+ * Failure injection for tests: while on (process-wide), every bounded wait of
+ * the full -> band reduction's grid barrier and of the bulge chase that is not
+ * already satisfied at its first poll gives up at once, exactly as if its 10 s
+ * limit had passed.  Every kernel still runs to its normal exit; the solves then
+ * report GEP_INFO_WAIT_TIMEOUT in info.  Off by default; affects launches
+ * enqueued while it is on.  Returns GEP_OK.
+ */
+int gep_debug_force_wait_timeout(int on);
+
+/*
+ * Failure injection for tests: while on (process-wide), the divide-and-conquer
+ * tridiagonal eigensolver's leaf iteration cap is zero, so the first leaf that
+ * needs an implicit QL iteration reports non-convergence through info
+ * (k in [1, M], the leaf's first eigenvalue index + 1), the path a real
+ * non-convergence takes.  Off by default.  Returns GEP_OK.
+ */
+int gep_debug_force_eig_failure(int on);
 
 #ifdef __cplusplus
 }

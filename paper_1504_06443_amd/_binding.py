@@ -17,6 +17,10 @@ GEP_ERR_ARG = -1
 GEP_ERR_WORKSPACE = -2
 GEP_ERR_HIP = -3
 
+# device info codes besides LAPACK's (include/gep.h)
+INFO_WAIT_TIMEOUT = -1
+INFO_REFINE_FAILED = -2
+
 
 class GEPError(RuntimeError):
     def __init__(self, status: int, where: str, bad_arg: int = 0):
@@ -71,6 +75,8 @@ SIGNATURES = {
     "gep_probe_enable": (INT, [INT]),
     "gep_probe_read": (INT, [INT, P, P, P]),
     "gep_probe_name": (ctypes.c_char_p, [INT]),
+    "gep_debug_force_wait_timeout": (INT, [INT]),
+    "gep_debug_force_eig_failure": (INT, [INT]),
 }
 
 

@@ -5,7 +5,8 @@ import ctypes
 
 import torch
 
-from ._binding import JOB_VALUES, JOB_VECTORS, PREC_FP64, PREC_MIXED, check, lib
+from ._binding import (INFO_REFINE_FAILED, INFO_WAIT_TIMEOUT, JOB_VALUES, JOB_VECTORS, PREC_FP64,
+                       PREC_MIXED, check, lib)
 
 PHASES = ("R1", "R2-4", "S1", "S2", "S3", "S4", "S5", "R5", "REF", "F")
 
@@ -40,6 +41,12 @@ def _raise_info(info: torch.Tensor, M: int, where: str) -> None:
     v = int(info.item())
     if v == 0:
         return
+    if v == INFO_WAIT_TIMEOUT:
+        raise torch.linalg.LinAlgError(f"{where}: a bounded wait between GPU workgroups timed "
+                                       f"out; the result is not valid (info={v})")
+    if v == INFO_REFINE_FAILED:
+        raise torch.linalg.LinAlgError(f"{where}: the mixed-precision refinement met a block of "
+                                       f"Y^T B Y that is not positive definite (info={v})")
     if v > M:
         raise torch.linalg.LinAlgError(f"{where}: the leading minor of order {v - M} of B is "
                                        f"not positive definite (info={v})")

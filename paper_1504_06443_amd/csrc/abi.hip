@@ -119,6 +119,7 @@ struct Plan {
   double *L, *Linv, *tmp, *C, *T1, *band, *d, *e, *V2, *tau2, *bounds;
   double* Zd;     // partial spectrum: the tridiagonal solver's M x M eigenvectors
   int32_t *sync, *err;
+  int32_t* info;  // the caller's info word (device), set by the solve
   char* scratch;  // phase scratch (reused by S1, S3, S4, S5)
   size_t scratch_bytes;
 };
@@ -166,6 +167,7 @@ void carve(Plan& p, Arena& a, int64_t M, bool vectors, bool mixed = false, bool 
   p.refine_ws = nullptr;
   p.refine_bytes = 0;
   p.coupling = nullptr;
+  p.info = nullptr;
   if (mixed) {
     p.refine_bytes = refine_workspace(M);
     p.refine_ws = a.take<char>(p.refine_bytes);
@@ -198,6 +200,7 @@ void reduce_steps(const Plan& p, const double* A, int64_t lda, const double* B, 
 BandReduction band_of(const Plan& p) {
   BandReduction r;
   r.n = p.M; r.b = p.b; r.C = p.C; r.ldc = p.M; r.T = p.T1; r.band = p.band; r.ldband = p.ldband;
+  r.info = p.info;
   return r;
 }
 
@@ -205,6 +208,7 @@ BulgeChase chase_of(const Plan& p) {
   BulgeChase c;
   c.n = p.M; c.b = p.b; c.band = p.band; c.ldband = p.ldband; c.d = p.d; c.e = p.e;
   c.V = p.V2; c.tau = p.tau2; c.kmax = p.kmax; c.sync = p.sync; c.err = p.err;
+  c.info = p.info;
   return c;
 }
 
@@ -243,6 +247,7 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
   a.base = (char*)workspace;
   a.cap = ws_bytes;
   carve(p, a, M, vectors, mixed, partial);
+  p.info = info;
   Prof prof(s);
   Prof* pp = prof_on ? &prof : nullptr;
   const MathMode trailing = mixed ? MathMode::Fp32 : MathMode::Fp64;
@@ -288,7 +293,7 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
     Arena ra;
     ra.base = p.refine_ws;
     ra.cap = p.refine_bytes;
-    refine(M, A, lda, B, ldb, Y, ldy, lambda, p.L, p.C, ra, p.coupling, s);
+    refine(M, A, lda, B, ldb, Y, ldy, lambda, p.L, p.C, ra, p.coupling, info, s);
   }
   if (pp) pp->mark(9);
   if (k > 0) {
@@ -348,6 +353,7 @@ void solve_cholfree(int64_t M, const double* A, int64_t lda, const double* B, in
   a.cap = ws_bytes;
   double *W = nullptr, *dB = nullptr;
   carve_cholfree(p, a, M, &W, &dB);
+  p.info = info;
   Prof prof(s);
   Prof* pp = prof_on ? &prof : nullptr;
   MathScope fp64(MathMode::Fp64);
@@ -493,6 +499,7 @@ void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const doubl
   a.base = (char*)workspace;
   a.cap = ws_bytes;
   carve(p, a, M, true);
+  p.info = info;
   double* R = a.take<double>((size_t)M * M);
   Prof prof(s);
   Prof* pp = prof_on ? &prof : nullptr;
@@ -1087,6 +1094,16 @@ int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k,
     gemm(g, (hipStream_t)stream);
     return GEP_OK;
   });
+}
+
+int gep_debug_force_wait_timeout(int on) {
+  set_force_wait_timeout(on != 0);
+  return GEP_OK;
+}
+
+int gep_debug_force_eig_failure(int on) {
+  set_force_eig_failure(on != 0);
+  return GEP_OK;
 }
 
 int gep_profile_enable(int on) {

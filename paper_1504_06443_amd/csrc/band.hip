@@ -53,8 +53,9 @@ struct PanelArgs {
   int64_t ldband, col0;
   int b;
   int rows_per;
-  int32_t* err;
+  int32_t* err;     // sticky across the panels of one reduction
   uint64_t timeout_ticks;
+  int force_fail;   // debug: a barrier not passed at its first poll gives up
 };
 
 __device__ bool grid_barrier(const PanelArgs& a, unsigned target) {
@@ -65,7 +66,7 @@ __device__ bool grid_barrier(const PanelArgs& a, unsigned target) {
     const uint64_t t0 = wall_clock64();
     ok = 1;
     while (__hip_atomic_load(a.bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-      if (wall_clock64() - t0 > a.timeout_ticks) {
+      if (a.force_fail || wall_clock64() - t0 > a.timeout_ticks) {
         __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
@@ -108,6 +109,19 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
   const int64_t r0 = (int64_t)g * a.rows_per;
   int nr = (int)((a.n - r0) < a.rows_per ? (a.n - r0) : a.rows_per);
   if (nr < 0) nr = 0;
+  // After a failed barrier (this panel or an earlier one) the reduction is
+  // abandoned: the remaining panels leave at once with every reflector the
+  // identity (tau = 0), so the later steps run on finite data, and the caller
+  // learns of the failure through info.
+  __shared__ int failed_sh;
+  if (tid == 0)
+    failed_sh = __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+  __syncthreads();
+  if (failed_sh) {
+    if (g == 0)
+      for (int c = tid; c < w; c += NT) a.tau[c] = 0.0;
+    return;
+  }
   // load the slice
   for (int j = 0; j < w; ++j)
     for (int i = tid; i < nr; i += NT) Ps[i * LDP + j] = a.P[(r0 + i) + (int64_t)j * a.ld];
@@ -146,7 +160,11 @@ __global__ void __launch_bounds__(NT) panel_qr_coop(PanelArgs a) {
       const int li = (int)(c - r0);
       for (int q = c + tid; q < w; q += NT) cst(&top[q], Ps[li * LDP + q]);
     }
-    if (!grid_barrier(a, (unsigned)(G * (c + 1)))) return;
+    if (!grid_barrier(a, (unsigned)(G * (c + 1)))) {
+      if (g == 0)
+        for (int cc = tid; cc < w; cc += NT) a.tau[cc] = 0.0;
+      return;
+    }
     // Every workgroup reduces the partials in the same fixed order, so all derive
     // the identical reflector.  Thread (quarter, q) sums partials quarter,
     // quarter + 4, ... of column q, with all of its remote loads in flight at once
@@ -377,13 +395,11 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
   int32_t* err = ws.take<int32_t>(1);
   fill_i32((int32_t*)bar, npanels + 1, 0, s);
   fill_i32(err, 1, 0, s);
+  fill_f64(tau, b, 0.0, s);
   fill_f64(r.band, r.ldband * N, 0.0, s);
   const int coop_max = coop_blocks();
-  int dev = 0, rate_khz = 0;
-  GEP_HIP(hipGetDevice(&dev));
-  GEP_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
-  if (rate_khz <= 0) rate_khz = 100000;
-  const uint64_t timeout_ticks = (uint64_t)rate_khz * 1000ull * 10ull;
+  const uint64_t timeout_ticks = wait_limit_ticks();
+  const int force_fail = force_wait_timeout() ? 1 : 0;
 
   // Diagonal block of the panel at col0 into the band, then the QR of the n x w
   // panel below it (reflectors stay in place, R goes to the band) and its T.
@@ -400,6 +416,7 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
       pa.bar = bar + (col0 / b); pa.tau = tau; pa.band = r.band; pa.ldband = r.ldband;
       pa.col0 = col0; pa.b = b; pa.rows_per = (int)cdiv(n, Gn); pa.err = err;
       pa.timeout_ticks = timeout_ticks;
+      pa.force_fail = force_fail;
       if (pa.rows_per > 256) throw HipError{hipErrorInvalidValue, "panel too tall"};
       // Householder QR of an n x kmax panel: 2 n kmax^2 - 2 kmax^3 / 3 flops
       ProbeScope probe(PROBE_PANEL_QR, s,
@@ -560,6 +577,7 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
     }
     col0 += 2 * b;
   }
+  raise_info_if(err, r.info, INFO_WAIT_TIMEOUT, s);
 }
 
 

@@ -191,6 +191,7 @@ struct ChaseArgs {
   int32_t* err;
   int64_t nsweeps;
   uint64_t timeout_ticks;
+  int force_fail;  // debug: a wait not satisfied at its first poll gives up
 };
 
 __device__ inline int64_t positions(int64_t n, int b, int64_t s) {
@@ -210,7 +211,7 @@ __device__ bool wait_for(const ChaseArgs& a, int64_t s, int32_t need) {
       return true;
     }
     if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
-    if (wall_clock64() - t0 > a.timeout_ticks) {
+    if (a.force_fail || wall_clock64() - t0 > a.timeout_ticks) {
       __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return false;
     }
@@ -1011,7 +1012,9 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
   const int64_t n = c.n;
   if (c.b > MAXB || c.b < 1) throw HipError{hipErrorInvalidValue, "band width"};
   const int64_t nsweeps = n > 2 ? n - 2 : 0;
+  // Reflectors a failed chase never reaches stay the identity (V = 0, tau = 0).
   if (c.V) fill_f64(c.V, (int64_t)sb2st_block_storage(n, c.b), 0.0, s);
+  if (c.tau) fill_f64(c.tau, (int64_t)sb2st_reflector_count(n, c.b), 0.0, s);
   if (nsweeps > 0) {
     int32_t* progress = c.sync;
     int32_t* ticket = c.sync + n;
@@ -1020,11 +1023,8 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     ChaseArgs a;
     a.n = n; a.b = c.b; a.band = c.band; a.ldband = c.ldband; a.V = c.V; a.tau = c.tau;
     a.kmax = c.kmax; a.progress = progress; a.ticket = ticket; a.err = c.err; a.nsweeps = nsweeps;
-    int dev = 0, rate_khz = 0;
-    GEP_HIP(hipGetDevice(&dev));
-    GEP_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
-    if (rate_khz <= 0) rate_khz = 100000;
-    a.timeout_ticks = (uint64_t)rate_khz * 1000ull * 10ull;  // 10 s for any single wait
+    a.timeout_ticks = wait_limit_ticks();  // 10 s for any single wait
+    a.force_fail = force_wait_timeout() ? 1 : 0;
     // Sweep s + 1 trails sweep s by about two positions, so at most about half of
     // a sweep's positions are ever worked on at once: more workgroups would only
     // spin (and, in batched solves, keep other instances' chases off the CUs).
@@ -1035,6 +1035,7 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     ProbeScope probe(PROBE_CHASE, s, 6.0 * c.b * (double)n * (double)n);
     hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(CNT), 0, s, a);
     GEP_LAUNCH_CHECK();
+    raise_info_if(c.err, c.info, INFO_WAIT_TIMEOUT, s);
   }
   hipLaunchKernelGGL(extract_tridiag, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n,
                      (const double*)c.band, c.ldband, c.d, c.e);

@@ -134,5 +134,28 @@ void set_matrix(int64_t m, int64_t n, double offdiag, double diag, double* dst, 
 void zero_upper(int64_t n, double* dst, int64_t ldd, hipStream_t s);
 void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 void fill_f64(double* p, int64_t n, double v, hipStream_t s);
+// Enqueue: if *flag != 0, set *info = code unless info already holds a failure.
+// A one-thread kernel, so it needs no host synchronisation and can be captured.
+void raise_info_if(const int32_t* flag, int32_t* info, int32_t code, hipStream_t s);
+
+// Device-side failure codes written to info besides the LAPACK ones (mirrored in
+// gep.h): a bounded wait between workgroups gave up, or the mixed-precision
+// refinement met a block of Y^T B Y that is not positive definite.
+constexpr int32_t INFO_WAIT_TIMEOUT = -1;
+constexpr int32_t INFO_REFINE_FAILED = -2;
+
+// Debug switch for the bounded waits of the band reduction's grid barrier and the
+// bulge chase: when set, every such wait that is not already satisfied at its
+// first poll gives up as if its time limit had passed (so the failure path can be
+// exercised while every kernel still exits normally).  Off by default.
+void set_force_wait_timeout(bool on);
+bool force_wait_timeout();
+// Debug switch for the tridiagonal eigensolver: when set, the leaf solver's
+// iteration cap is zero, so the first leaf that needs a QL iteration reports
+// non-convergence (info = its first index + 1), as a real failure would.
+void set_force_eig_failure(bool on);
+bool force_eig_failure();
+// Wall-clock ticks a bounded wait may last before it gives up (10 s).
+uint64_t wait_limit_ticks();
 
 }  // namespace gep

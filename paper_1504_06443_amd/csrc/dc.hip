@@ -80,7 +80,8 @@ struct Work {
 // then sort.
 __global__ void __launch_bounds__(64)
 leaf_kernel(int64_t n, int D, const double* __restrict__ d, const double* __restrict__ e,
-            double* __restrict__ lam, double* __restrict__ Z, int64_t ldz, int32_t* info) {
+            double* __restrict__ lam, double* __restrict__ Z, int64_t ldz, int32_t* info,
+            int maxit) {
   __shared__ double zs[LEAF][LEAF + 1];
   __shared__ double dl[LEAF], el[LEAF], cs[LEAF], sn[LEAF];
   __shared__ int nrot_sh, fail_sh, top_sh;
@@ -110,7 +111,7 @@ leaf_kernel(int64_t n, int D, const double* __restrict__ d, const double* __rest
         }
         int nrot = 0;
         if (mm != l) {
-          if (++iter > 60) {
+          if (++iter > maxit) {
             fail_sh = 1;
           } else {
             double g = (dl[l + 1] - dl[l]) / (2.0 * el[l]);
@@ -750,8 +751,10 @@ void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, 
     host_sized = cs == hipStreamCaptureStatusNone;
   }
   set_matrix(n, n, 0.0, 0.0, Z, ldz, s);
+  // implicit QL converges in a few iterations per eigenvalue; 60 is the cap
+  const int maxit = force_eig_failure() ? 0 : 60;
   hipLaunchKernelGGL(leaf_kernel, dim3((unsigned)((int64_t)1 << D)), dim3(64), 0, s, n, D, d, e, lam,
-                     Z, ldz, info);
+                     Z, ldz, info, maxit);
   GEP_LAUNCH_CHECK();
   for (int t = D - 1; t >= 0; --t) {
     const unsigned P = 1u << t;

@@ -41,6 +41,8 @@ struct BandReduction {
   double* band = nullptr;
   int64_t ldband = 0;
   bool coop = true;      // cooperative launch of the panel QR
+  int32_t* info = nullptr;  // device: INFO_WAIT_TIMEOUT if a panel's grid barrier
+                            // gave up (optional)
 };
 size_t sy2sb_workspace(int64_t n, int b);
 void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s);
@@ -62,6 +64,7 @@ struct BulgeChase {
   int64_t kmax = 0;        // reflector positions per sweep = ceil((n-1)/b)
   int32_t* sync = nullptr; // device scratch: progress flags (n + 8 ints)
   int32_t* err = nullptr;  // device: set to nonzero if a wait timed out
+  int32_t* info = nullptr; // device: INFO_WAIT_TIMEOUT if so (optional)
 };
 size_t sb2st_reflector_count(int64_t n, int b);
 size_t sb2st_block_storage(int64_t n, int b);
@@ -95,8 +98,10 @@ void sign_fix(int64_t n, int64_t ncols, double* Y, int64_t ldy, hipStream_t s);
 // ascending eigenpairs.  W1, W2: M x M scratch (leading dimension M).  Writes the
 // largest first-order coupling left between blocks to *coupling_out (device).
 size_t refine_workspace(int64_t M);
+// info (device, optional): INFO_REFINE_FAILED when a block's Y^T B Y is not
+// positive definite.
 void refine(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb, double* Y,
             int64_t ldy, double* lambda, double* W1, double* W2, Arena& ws, double* coupling_out,
-            hipStream_t s);
+            int32_t* info, hipStream_t s);
 
 }  // namespace gep

@@ -445,7 +445,7 @@ size_t refine_workspace(int64_t M) {
 
 void refine(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb, double* Y,
             int64_t ldy, double* lambda, double* W1, double* W2, Arena& ws, double* coupling_out,
-            hipStream_t s) {
+            int32_t* info, hipStream_t s) {
   if (M <= 0) return;
   MathScope fp64(MathMode::Fp64);
   RefineBufs r = carve_refine(M, ws);
@@ -484,6 +484,7 @@ void refine(int64_t M, const double* A, int64_t lda, const double* B, int64_t ld
                      (const double*)T, M, (const int32_t*)r.starts, (const int32_t*)r.nblk, r.K,
                      M, r.err);
   GEP_LAUNCH_CHECK();
+  raise_info_if(r.err, info, INFO_REFINE_FAILED, s);
   // S' = K^T (S K) into W2, T' = K^T (T K) into S's buffer
   block_product(M, 0, r, S, M, W1, M, s);
   block_product(M, 1, r, W1, M, W2, M, s);

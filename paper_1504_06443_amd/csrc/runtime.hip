@@ -9,6 +9,8 @@ namespace gep {
 namespace {
 
 thread_local MathMode t_mode = MathMode::Fp64;
+bool g_force_timeout = false;
+bool g_force_eig_failure = false;
 
 struct ProbeRecord {
   hipEvent_t start, stop;
@@ -34,6 +36,19 @@ hipEvent_t take_event() {
 }  // namespace
 
 MathMode math_mode() { return t_mode; }
+
+void set_force_wait_timeout(bool on) { g_force_timeout = on; }
+bool force_wait_timeout() { return g_force_timeout; }
+void set_force_eig_failure(bool on) { g_force_eig_failure = on; }
+bool force_eig_failure() { return g_force_eig_failure; }
+
+uint64_t wait_limit_ticks() {
+  int dev = 0, rate_khz = 0;
+  GEP_HIP(hipGetDevice(&dev));
+  GEP_HIP(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+  if (rate_khz <= 0) rate_khz = 100000;
+  return (uint64_t)rate_khz * 1000ull * 10ull;
+}
 
 MathScope::MathScope(MathMode m) : saved(t_mode) { t_mode = m; }
 MathScope::~MathScope() { t_mode = saved; }

@@ -1,0 +1,325 @@
+// Tuned blocking and launch parameters.  Each parameter has a built-in default
+// rule; a table of (parameter, range of orders M, value) entries can replace it
+// for the orders it covers.  The table is read once, when the library is first
+// used, from the JSON file named by GEP_TUNE_FILE or else tuning.json beside
+// libgep.so (written by the package's autotune.py from timings on the GPU), and
+// can be changed at run time (gep_tune_set / gep_tune_load / gep_tune_clear).
+//
+// Accepted file format (other keys and fields are ignored):
+//   {"parameters": {"<name>": [{"m_lo": 64, "m_hi": 127, "value": 16, ...}, ...]}}
+#include <dlfcn.h>
+
+#include <cctype>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../include/gep.h"
+#include "common.h"
+
+namespace gep {
+namespace {
+
+struct Range {
+  int64_t lo, hi, value;
+};
+
+struct Param {
+  const char* name;
+  int64_t vmin, vmax;
+};
+
+// The tunable parameters and their admissible values.
+const Param kParams[] = {
+    {"band_width", 1, 64},            // full -> band reduction width b
+    {"q2_wide_min_cols", 0, INT64_MAX},  // Q2 with two column groups per wave from this many columns
+    {"dc_leaf", 8, 64},               // divide-and-conquer leaf order
+    {"symm_split_rows", 1, INT64_MAX},   // the band reduction's symmetric product splits K from here
+    {"chase_extra_groups", 0, 512},   // bulge chase workgroups beyond half the positions
+};
+
+bool known(const std::string& k, const Param** out) {
+  for (const Param& p : kParams)
+    if (k == p.name) {
+      if (out) *out = &p;
+      return true;
+    }
+  return false;
+}
+
+std::mutex g_mu;
+bool g_loaded = false;
+std::map<std::string, std::vector<Range>> g_table;   // from the file
+std::map<std::string, std::vector<Range>> g_over;    // gep_tune_set
+
+// ---------------------------------------------------------------- minimal JSON
+struct J {
+  enum T { Null, Num, Str, Arr, Obj, Bool } t = Null;
+  double num = 0.0;
+  std::string str;
+  std::vector<J> arr;
+  std::vector<std::pair<std::string, J>> obj;
+  const J* get(const char* k) const {
+    for (auto& kv : obj)
+      if (kv.first == k) return &kv.second;
+    return nullptr;
+  }
+};
+
+struct Parser {
+  const std::string& s;
+  size_t i = 0;
+  explicit Parser(const std::string& src) : s(src) {}
+  void ws() {
+    while (i < s.size() && std::isspace((unsigned char)s[i])) ++i;
+  }
+  bool lit(const char* w) {
+    const size_t n = std::strlen(w);
+    if (s.compare(i, n, w) != 0) return false;
+    i += n;
+    return true;
+  }
+  bool value(J& out, int depth) {
+    if (depth > 32) return false;
+    ws();
+    if (i >= s.size()) return false;
+    const char c = s[i];
+    if (c == '{') {
+      ++i;
+      out.t = J::Obj;
+      ws();
+      if (i < s.size() && s[i] == '}') { ++i; return true; }
+      for (;;) {
+        J key;
+        ws();
+        if (!(i < s.size() && s[i] == '"') || !string(key.str)) return false;
+        ws();
+        if (!(i < s.size() && s[i] == ':')) return false;
+        ++i;
+        J v;
+        if (!value(v, depth + 1)) return false;
+        out.obj.emplace_back(key.str, std::move(v));
+        ws();
+        if (i < s.size() && s[i] == ',') { ++i; continue; }
+        if (i < s.size() && s[i] == '}') { ++i; return true; }
+        return false;
+      }
+    }
+    if (c == '[') {
+      ++i;
+      out.t = J::Arr;
+      ws();
+      if (i < s.size() && s[i] == ']') { ++i; return true; }
+      for (;;) {
+        J v;
+        if (!value(v, depth + 1)) return false;
+        out.arr.push_back(std::move(v));
+        ws();
+        if (i < s.size() && s[i] == ',') { ++i; continue; }
+        if (i < s.size() && s[i] == ']') { ++i; return true; }
+        return false;
+      }
+    }
+    if (c == '"') {
+      out.t = J::Str;
+      return string(out.str);
+    }
+    if (lit("true")) { out.t = J::Bool; out.num = 1; return true; }
+    if (lit("false")) { out.t = J::Bool; out.num = 0; return true; }
+    if (lit("null")) { out.t = J::Null; return true; }
+    const char* b = s.c_str() + i;
+    char* e = nullptr;
+    out.num = std::strtod(b, &e);
+    if (e == b) return false;
+    out.t = J::Num;
+    i += (size_t)(e - b);
+    return true;
+  }
+  bool string(std::string& out) {
+    ++i;  // opening quote
+    while (i < s.size() && s[i] != '"') {
+      if (s[i] == '\\') {
+        if (i + 1 >= s.size()) return false;
+        const char e = s[i + 1];
+        if (e == 'u') {
+          if (i + 5 >= s.size()) return false;
+          out += '?';  // names here are ASCII; other code points are not needed
+          i += 6;
+          continue;
+        }
+        out += (e == 'n') ? '\n' : (e == 't') ? '\t' : e;
+        i += 2;
+        continue;
+      }
+      out += s[i++];
+    }
+    if (i >= s.size()) return false;
+    ++i;
+    return true;
+  }
+};
+
+bool whole(double x, int64_t* out) {
+  if (!(x >= -9.2e18 && x <= 9.2e18)) return false;
+  const int64_t v = (int64_t)x;
+  if ((double)v != x) return false;
+  *out = v;
+  return true;
+}
+
+// Parse `text` into `table`; false (table untouched) on any malformed entry.
+bool parse_table(const std::string& text, std::map<std::string, std::vector<Range>>& table) {
+  J root;
+  Parser p(text);
+  if (!p.value(root, 0) || root.t != J::Obj) return false;
+  p.ws();
+  if (p.i != text.size()) return false;
+  const J* params = root.get("parameters");
+  std::map<std::string, std::vector<Range>> t;
+  if (params) {
+    if (params->t != J::Obj) return false;
+    for (auto& kv : params->obj) {
+      const Param* prm = nullptr;
+      if (!known(kv.first, &prm)) continue;  // parameters of other versions
+      if (kv.second.t != J::Arr) return false;
+      for (const J& e : kv.second.arr) {
+        const J* lo = e.get("m_lo");
+        const J* hi = e.get("m_hi");
+        const J* v = e.get("value");
+        Range r;
+        if (!lo || !hi || !v || lo->t != J::Num || hi->t != J::Num || v->t != J::Num) return false;
+        if (!whole(lo->num, &r.lo) || !whole(hi->num, &r.hi) || !whole(v->num, &r.value))
+          return false;
+        if (r.lo < 0 || r.hi < r.lo || r.value < prm->vmin || r.value > prm->vmax) return false;
+        t[kv.first].push_back(r);
+      }
+    }
+  }
+  table.swap(t);
+  return true;
+}
+
+std::string default_path() {
+  if (const char* env = std::getenv("GEP_TUNE_FILE")) return env;
+  Dl_info info;
+  if (dladdr((void*)&gep_tune_get, &info) && info.dli_fname) {
+    std::string so = info.dli_fname;
+    const size_t slash = so.rfind('/');
+    return (slash == std::string::npos ? std::string(".") : so.substr(0, slash)) + "/tuning.json";
+  }
+  return "tuning.json";
+}
+
+// Loads the table from `path` (empty: the default location).  Returns the
+// number of entries, 0 when there is no file, -1 when it cannot be parsed.
+int load_locked(const std::string& path_in) {
+  const std::string path = path_in.empty() ? default_path() : path_in;
+  g_loaded = true;
+  std::ifstream f(path);
+  if (!f) {
+    g_table.clear();
+    return path_in.empty() ? 0 : -1;
+  }
+  std::stringstream ss;
+  ss << f.rdbuf();
+  std::map<std::string, std::vector<Range>> t;
+  if (!parse_table(ss.str(), t)) return -1;
+  g_table.swap(t);
+  int n = 0;
+  for (auto& kv : g_table) n += (int)kv.second.size();
+  return n;
+}
+
+bool lookup(const std::map<std::string, std::vector<Range>>& t, const std::string& k, int64_t M,
+            int64_t* out) {
+  auto it = t.find(k);
+  if (it == t.end()) return false;
+  // the last entry covering M wins (later overrides refine earlier ones)
+  for (auto r = it->second.rbegin(); r != it->second.rend(); ++r)
+    if (M >= r->lo && M <= r->hi) {
+      *out = r->value;
+      return true;
+    }
+  return false;
+}
+
+// The built-in rules, used where no table entry covers M.
+int64_t default_value(const std::string& k, int64_t M) {
+  if (k == "band_width") return M >= 2048 ? 64 : (M >= 256 ? 32 : 16);
+  if (k == "q2_wide_min_cols") {
+    // one 128-column workgroup per CU
+    static int cus = 0;
+    if (cus == 0) {
+      int dev = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          cus <= 0)
+        cus = 256;
+    }
+    return 128 * (int64_t)cus;
+  }
+  if (k == "dc_leaf") return 64;
+  if (k == "symm_split_rows") return 2048;
+  if (k == "chase_extra_groups") return 8;
+  return -1;
+}
+
+}  // namespace
+
+int64_t tune(const char* key, int64_t M) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  if (!g_loaded) load_locked("");
+  int64_t v = 0;
+  if (lookup(g_over, key, M, &v)) return v;
+  if (lookup(g_table, key, M, &v)) return v;
+  return default_value(key, M);
+}
+
+}  // namespace gep
+
+using namespace gep;
+
+extern "C" {
+
+int gep_tune_load(const char* path) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  const int n = load_locked(path ? std::string(path) : std::string());
+  return n < 0 ? GEP_ERR_ARG : n;
+}
+
+int gep_tune_set(const char* key, int64_t m_lo, int64_t m_hi, int64_t value) {
+  const Param* p = nullptr;
+  if (!key || !known(key, &p)) return GEP_ERR_ARG;
+  if (m_lo < 0 || m_hi < m_lo) return GEP_ERR_ARG;
+  if (value < p->vmin || value > p->vmax) return GEP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_over[key].push_back(Range{m_lo, m_hi, value});
+  return GEP_OK;
+}
+
+int gep_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_over.clear();
+  g_table.clear();
+  g_loaded = true;
+  return GEP_OK;
+}
+
+int64_t gep_tune_get(const char* key, int64_t M) {
+  if (!key || !known(key, nullptr)) return -1;
+  return tune(key, M);
+}
+
+int gep_tune_reset_overrides(void) {
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_over.clear();
+  return GEP_OK;
+}
+
+}  // extern "C"

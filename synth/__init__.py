@@ -155,6 +155,18 @@ def unit_direction(M: int, seed: int) -> np.ndarray:
     return E / np.linalg.norm(E)
 
 
+def probe_matrix(M: int, k: int, seed: int) -> np.ndarray:
+    """M x k i.i.d. N(0,1) probe vectors (random projections for comparing large
+    matrices through a few products)."""
+    return np.random.default_rng(seed).standard_normal((M, k))
+
+
+def sample_pairs(M: int, count: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """`count` uniformly drawn (row, column) index pairs of an M x M matrix."""
+    g = np.random.default_rng(seed)
+    return g.integers(0, M, count), g.integers(0, M, count)
+
+
 def toeplitz_tridiag(M: int, a: float, b: float) -> np.ndarray:
     T = np.zeros((M, M))
     T[np.diag_indices(M)] = a

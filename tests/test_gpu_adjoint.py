@@ -53,24 +53,72 @@ def _loss_difference(lp, Yp, lm, Ym, G, nocc):
     return ((lp[:nocc] - lm[:nocc]).sum() + (G * (Pp - Pm)).sum()).item()
 
 
-def test_c5_gradient_vs_central_differences(gpu):
+@pytest.fixture(scope="module")
+def c5(gpu):
+    """The 4096 gradient workload: inputs on the GPU, and the GPU's forward
+    eigenvalues and gradient of L = sum_{k <= M/2} lambda_k + tr(G Y_occ Y_occ^T)."""
+    gep = _gep()
+    M = 4096
+    say("[adjoint] c5: generating and differentiating")
+    A, B = synth.workload("m4096_grad")
+    G = synth.symmetric_normal(M, 5001, 1.0 / np.sqrt(M))
+    dA0, dB0, dG = to_gpu(A), to_gpu(B), to_gpu(G)
+    Ad = dA0.clone().requires_grad_(True)
+    Bd = dB0.clone().requires_grad_(True)
+    lam, Y = gep.GEPFunction.apply(Ad, Bd)
+    L = _loss_torch(lam, Y, dG, M // 2)
+    L.backward()
+    return {"A": A, "dA": dA0, "dB": dB0, "dG": dG, "lam": lam.detach(), "gA": Ad.grad,
+            "gB": Bd.grad}
+
+
+def test_c5_gradient_vs_stored_oracle(c5):
+    """The GPU gradient at M = 4096 against the oracle's gradient on the oracle's
+    own eigenpairs (tests/golden/make_golden.py --gradient, oracle only), compared
+    through what is stored of it: the products with 8 seeded probe vectors, both
+    diagonals and 4096 sampled entries, each within 1e-8 relative (the oracle-
+    gradient bar of the 4096 gradient workload), and the forward eigenvalues within
+    1e-11 |A|_1."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "m4096_grad_oracle.npz")
+    ref = np.load(path)
+    M = c5["A"].shape[0]
+    n1 = oracle.norm1_sym_lower(c5["A"])
+    err_lam = np.abs(to_np(c5["lam"]) - ref["lam"]).max() / n1
+    say(f"[adjoint] c5 eigenvalues vs oracle: {err_lam:.2e}")
+    assert err_lam <= 1e-11, err_lam
+    X = synth.probe_matrix(M, 8, 5201)
+    ii, jj = synth.sample_pairs(M, 4096, 5202)
+    gA, gB = to_np(c5["gA"]), to_np(c5["gB"])
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+    checks = {
+        "A_bar X": rel(gA @ X, ref["A_bar_X"]), "B_bar X": rel(gB @ X, ref["B_bar_X"]),
+        "diag A_bar": rel(np.diag(gA), ref["A_bar_diag"]),
+        "diag B_bar": rel(np.diag(gB), ref["B_bar_diag"]),
+        "A_bar samples": rel(gA[ii, jj], ref["A_bar_samples"]),
+        "B_bar samples": rel(gB[ii, jj], ref["B_bar_samples"]),
+        "|A_bar|_F": abs(np.linalg.norm(gA) / float(ref["A_bar_fro"]) - 1.0),
+        "|B_bar|_F": abs(np.linalg.norm(gB) / float(ref["B_bar_fro"]) - 1.0),
+    }
+    for k, v in checks.items():
+        say(f"  {k}: relative difference {v:.2e}")
+    assert max(checks.values()) <= 1e-8, checks
+
+
+def test_c5_gradient_vs_central_differences(c5):
     """L = sum_{k <= M/2} lambda_k + tr(G Y_occ Y_occ^T) at M = 4096: dL/dA, dL/dB
     against central differences (h = 1e-6) on 20 unit directions (7 A-only, 7 B-only,
     6 joint)."""
     import torch
     gep = _gep()
-    M = 4096
-    say("[adjoint] c5 FD: generating")
-    A, B = synth.workload("m4096_grad")
-    G = synth.symmetric_normal(M, 5001, 1.0 / np.sqrt(M))
-    dA0, dB0, dG = to_gpu(A), to_gpu(B), to_gpu(G)
+    A = c5["A"]
+    M = A.shape[0]
+    dA0, dB0, dG = c5["dA"], c5["dB"], c5["dG"]
+    gA, gB = c5["gA"], c5["gB"]
     nocc = M // 2
-    Ad = dA0.clone().requires_grad_(True)
-    Bd = dB0.clone().requires_grad_(True)
-    lam, Y = gep.GEPFunction.apply(Ad, Bd)
-    L = _loss_torch(lam, Y, dG, nocc)
-    L.backward()
-    gA, gB = Ad.grad, Bd.grad
     h = 1e-6
     # Noise floor of the central difference, divided by 2h: each occupied
     # eigenvalue of an FP64 solve is off by up to ~10 eps |A|_1 (the solver's

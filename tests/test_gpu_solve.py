@@ -263,3 +263,42 @@ def test_solve_explicit_inverse_indefinite_B_reports_info(gpu):
     B[40, 40] = -1.0
     with pytest.raises(torch.linalg.LinAlgError, match="order 41"):
         _gep().solve_explicit_inverse(to_gpu(A), to_gpu(B))
+
+
+@pytest.mark.parametrize("M", [17, 129, 600])
+def test_sign_convention_matches_oracle(gpu, M):
+    """The finishing step's sign convention (the entry of largest magnitude of
+    each eigenvector is positive) against the oracle's eigenvectors, column by
+    column.  Only simple eigenvalues (relative gap above 1e-6) are compared, and
+    columns whose largest entry has a rival of the opposite sign within 1e-6 of
+    its magnitude are skipped, since rounding may pick either there; for every
+    other column the two vectors must agree with the same sign (B-inner product
+    close to +1), so a solver that dropped or inverted the convention fails."""
+    say(f"[solve] sign convention M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 700 + M)
+    lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    lam, Y = to_np(lam), to_np(Y)
+    r = oracle.solve(A, B)
+    n1 = r.norm1
+    gaps = np.full(M, np.inf)
+    if M > 1:
+        d = np.diff(r.lam)
+        gaps[:-1] = d
+        gaps[1:] = np.minimum(gaps[1:], d)
+    compared = 0
+    for j in range(M):
+        if gaps[j] <= 1e-6 * n1:
+            continue
+        y = r.Y[:, j]
+        k = int(np.argmax(np.abs(y)))
+        assert y[k] > 0  # the oracle's own convention
+        rivals = np.abs(y[np.sign(y) != np.sign(y[k])])
+        if rivals.size and rivals.max() >= np.abs(y[k]) * (1 - 1e-6):
+            continue
+        g = Y[:, j]
+        kg = int(np.argmax(np.abs(g)))
+        assert g[kg] > 0, (j, g[kg])
+        c = float(g @ B @ y)
+        assert c > 1.0 - 1e-8, (j, c)
+        compared += 1
+    assert compared >= M // 2, compared
