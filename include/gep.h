@@ -106,6 +106,29 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
               size_t ws_bytes, int32_t* info, void* stream);
 
 /*
+ * gep_solve for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same solve
+ * with the same arguments except the workspace, which is a fixed array built into
+ * the library's device image (gep_noalloc_max_bytes() bytes, 272 MiB, held on
+ * each device the library runs on until the process ends).  Nothing is allocated
+ * by this call, and no phase timing events are recorded.
+ *   Limit: gep_workspace_size(M, job, prec) <= gep_noalloc_max_bytes(); every
+ *   M <= 2303 for FP64 eigenpairs (so every order of a batch in [64, 2048]),
+ *   M <= 1858 mixed, M <= 3889 eigenvalues only.  Larger problems return
+ *   GEP_ERR_WORKSPACE before any device work.
+ *   Every call on one device uses that device's single array: calls that overlap
+ *   in time on one device (other streams, other host threads) race and give wrong
+ *   results; calls on different devices do not interfere.  Each call clears the
+ *   parts of the array it relies on, so the previous call's contents do no harm.
+ *   Argument errors name the argument by its position (1 = M ... 11 = info).
+ */
+int gep_solve_noalloc(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double* lambda, double* Y, int64_t ldy, int job, int prec, int32_t* info,
+                      void* stream);
+/* Bytes of the fixed workspace gep_solve_noalloc uses on each device. */
+size_t gep_noalloc_max_bytes(void);
+
+/*
  * Partial spectrum: all M eigenvalues and the eigenvectors of the k smallest.
  * Electronic-structure calculations need eigenpairs on the order of the number
  * of electrons (section 2.1), and the eigenvector part of a solve,

@@ -51,6 +51,8 @@ SIGNATURES = {
     "gep_version": (ctypes.c_char_p, []),
     "gep_workspace_size": (SZ, [I64, INT, INT]),
     "gep_solve": (INT, [I64, P, I64, P, I64, P, P, I64, INT, INT, P, SZ, P, P]),
+    "gep_solve_noalloc": (INT, [I64, P, I64, P, I64, P, P, I64, INT, INT, P, P]),
+    "gep_noalloc_max_bytes": (SZ, []),
     "gep_workspace_size_lowest": (SZ, [I64, I64]),
     "gep_solve_lowest": (INT, [I64, P, I64, P, I64, I64, P, P, I64, P, SZ, P, P]),
     "gep_workspace_size_cholfree": (SZ, [I64]),

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <vector>
 
 #include "../../include/gep.h"
@@ -617,6 +618,34 @@ Workers& workers() {
   return w;
 }
 
+// ---------------------------------------------------------------- allocation-free solves
+// gep_solve_noalloc's workspace: one array per device, part of the library's
+// device image, so using it allocates nothing.  In host code `scratch` is only a
+// stand-in for the symbol: its device address comes from hipGetSymbolAddress,
+// once per device with that device current, and only that address is ever
+// passed to a kernel.  Every call on a device shares the array, so calls that
+// overlap on one device race; the solve clears everything it needs cleared.
+constexpr size_t NOALLOC_BYTES = (size_t)272 << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`.
+void* scratch_on_current_device() {
+  int dev = 0;
+  GEP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) throw HipError{hipErrorInvalidDevice, "device index"};
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    GEP_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) throw HipError{hipErrorInvalidSymbol, "scratch address"};
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 }  // namespace gep
 
@@ -677,6 +706,38 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
     return GEP_OK;
   });
 }
+
+int gep_solve_noalloc(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double* lambda, double* Y, int64_t ldy, int job, int prec, int32_t* info,
+                      void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (M > 0 && !lambda) return bad(6);
+  if (job != GEP_JOB_VALUES && job != GEP_JOB_VECTORS) return bad(9);
+  if (job == GEP_JOB_VECTORS) {
+    if (M > 0 && !Y) return bad(7);
+    if (ldy < m1) return bad(8);
+  }
+  if (prec != GEP_PREC_FP64 && !(prec == GEP_PREC_MIXED && job == GEP_JOB_VECTORS)) return bad(10);
+  if (!info) return bad(11);
+  const size_t need = gep_workspace_size(M, job, prec);
+  if (need > NOALLOC_BYTES) return GEP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    void* ws = scratch_on_current_device();
+    // no phase events: creating them is the one resource a profiled gep_solve adds
+    solve_one(M, A, lda, B, ldb, lambda, Y, ldy, job == GEP_JOB_VECTORS, ws, NOALLOC_BYTES, info,
+              s, true, false, prec == GEP_PREC_MIXED);
+    return GEP_OK;
+  });
+}
+
+size_t gep_noalloc_max_bytes(void) { return NOALLOC_BYTES; }
 
 size_t gep_workspace_size_lowest(int64_t M, int64_t k) {
   if (M <= 0) return 256;
