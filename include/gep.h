@@ -291,6 +291,13 @@ int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k,
  */
 int gep_profile_enable(int on);
 int gep_profile_read(double* ms, int n);
+/*
+ * Flops of the divide-and-conquer merge products of the last profiled gep_solve
+ * (job = VECTORS): 2 m n k summed over every merge's two products with their
+ * sizes after deflation, i.e. the data-dependent part of that phase's work.
+ * Valid once gep_profile_read has returned for that solve; 0 before any.
+ */
+double gep_profile_dc_flops(void);
 
 /*
  * Launch probes: when enabled, every launch of the probed kernels records a HIP
@@ -308,6 +315,49 @@ int gep_profile_read(double* ms, int n);
 int gep_probe_enable(int on);
 int gep_probe_read(int kernel, int64_t* launches, double* ms, double* flops);
 const char* gep_probe_name(int kernel);
+
+/*
+ * Tuned parameters.  The blocking and launch parameters below have built-in
+ * rules; a table of (parameter, orders m_lo..m_hi, value) entries replaces a
+ * rule for the orders it covers.  The table is read when the library is first
+ * used from the JSON file named by the environment variable GEP_TUNE_FILE, else
+ * from tuning.json beside libgep.so (written by the package's autotune.py from
+ * timings on the GPU); with no file the built-in rules apply.  Format:
+ *   {"parameters": {"band_width": [{"m_lo": 64, "m_hi": 127, "value": 16}, ...]}}
+ * (other keys and fields are ignored).  Parameters (admissible values):
+ *   band_width          width b of the full -> band reduction (1..64; built in:
+ *                       64 from order 2048, 32 from 256, else 16); b = 64 selects
+ *                       the register-window Q2 back transformation;
+ *   q2_wide_min_cols    Q2 back transformation with 32 columns per wave (one wave
+ *                       per SIMD) when at least this many columns are transformed
+ *                       (>= 0; built in: 2^40, i.e. always 16 per wave);
+ *   dc_leaf             largest leaf of the divide-and-conquer tree (8..64; 64);
+ *   symm_split_rows     the band reduction's symmetric products split their sum
+ *                       over workgroups from this many rows (>= 1; 2048);
+ *   chase_extra_groups  bulge chase workgroups beyond half the first sweep's
+ *                       positions (0..512; 8).
+ * Results depend on band_width and dc_leaf only through rounding; every
+ * parameter value gives a correct solve.  A batched instance and a single solve
+ * of the same order use the same values.
+ *
+ * gep_tune_load: (re)read the table from `path` (NULL: the default location,
+ *   where a missing file means no table).  Returns the number of entries read, or
+ *   GEP_ERR_ARG when the file is missing (explicit path) or malformed (the
+ *   previous table is kept then).
+ * gep_tune_set: add a run-time override for orders m_lo..m_hi (it takes
+ *   precedence over the table; the latest override covering an order wins).
+ *   GEP_ERR_ARG for an unknown parameter, an empty range or a value outside the
+ *   admissible ones.
+ * gep_tune_reset_overrides: drop every run-time override (the table stays).
+ * gep_tune_clear: drop the table and every override: built-in rules only.
+ * gep_tune_get: the value in effect for order M, or -1 for an unknown name.
+ * The table is process-wide; change it only while no solve is being enqueued.
+ */
+int gep_tune_load(const char* path);
+int gep_tune_set(const char* key, int64_t m_lo, int64_t m_hi, int64_t value);
+int gep_tune_reset_overrides(void);
+int gep_tune_clear(void);
+int64_t gep_tune_get(const char* key, int64_t M);
 
 /*
  * Failure injection for tests: while on (process-wide), every bounded wait of

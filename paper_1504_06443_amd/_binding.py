@@ -74,9 +74,15 @@ SIGNATURES = {
     "gep_dgemm": (INT, [INT, INT, INT, I64, I64, I64, DBL, P, I64, P, I64, DBL, P, I64, INT, P]),
     "gep_profile_enable": (INT, [INT]),
     "gep_profile_read": (INT, [P, INT]),
+    "gep_profile_dc_flops": (DBL, []),
     "gep_probe_enable": (INT, [INT]),
     "gep_probe_read": (INT, [INT, P, P, P]),
     "gep_probe_name": (ctypes.c_char_p, [INT]),
+    "gep_tune_load": (INT, [ctypes.c_char_p]),
+    "gep_tune_set": (INT, [ctypes.c_char_p, I64, I64, I64]),
+    "gep_tune_reset_overrides": (INT, []),
+    "gep_tune_clear": (INT, []),
+    "gep_tune_get": (I64, [ctypes.c_char_p, I64]),
     "gep_debug_force_wait_timeout": (INT, [INT]),
     "gep_debug_force_eig_failure": (INT, [INT]),
 }

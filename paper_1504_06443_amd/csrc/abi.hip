@@ -21,11 +21,9 @@ int bad(int idx) {
   return GEP_ERR_ARG;
 }
 
-int default_band(int64_t M) {
-  if (M >= 2048) return 64;
-  if (M >= 256) return 32;
-  return 16;
-}
+// Band width of the full -> band reduction (tuning table; by default 64 from
+// order 2048, 32 from 256, else 16).
+int default_band(int64_t M) { return (int)tune("band_width", M); }
 
 // ---------------------------------------------------------------- finishing
 __global__ void sign_fix_kernel(int64_t n, double* __restrict__ Y, int64_t ldy) {
@@ -93,6 +91,15 @@ bool g_prof = false;
 hipEvent_t g_ev[NPHASE + 1];
 bool g_ev_ok = false;
 bool g_ev_recorded = false;
+double* g_dc_flops = nullptr;  // pinned host: the last profiled solve's merge flops
+
+double* dc_flops_host() {
+  if (!g_dc_flops) {
+    GEP_HIP(hipHostMalloc((void**)&g_dc_flops, sizeof(double), hipHostMallocDefault));
+    *g_dc_flops = 0.0;
+  }
+  return g_dc_flops;
+}
 
 struct Prof {
   hipStream_t s;
@@ -273,7 +280,8 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
   {
     MathScope fp64(MathMode::Fp64);
     Arena sa = scratch_arena(p);
-    stedc(M, p.d, p.e, lambda, partial ? p.Zd : Y, partial ? M : ldy, info, sa, s);
+    stedc(M, p.d, p.e, lambda, partial ? p.Zd : Y, partial ? M : ldy, info, sa, s,
+          (pp && g_prof) ? dc_flops_host() : nullptr);
     if (partial && k > 0) copy_matrix(M, k, p.Zd, M, Y, ldy, s);
   }
   if (pp) pp->mark(5);
@@ -1194,6 +1202,8 @@ const char* gep_probe_name(int kernel) {
     default: return nullptr;
   }
 }
+
+double gep_profile_dc_flops(void) { return g_dc_flops ? *g_dc_flops : 0.0; }
 
 int gep_profile_read(double* ms, int n) {
   if (!g_prof || !g_ev_recorded || !ms) return 0;

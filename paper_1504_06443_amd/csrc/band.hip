@@ -21,7 +21,6 @@ namespace {
 
 constexpr int NT = 256;
 constexpr int MAXB = 64;  // largest supported band width
-constexpr int64_t SYMM_SPLIT_ROWS = 2048;
 
 // Band data shared between workgroups of one launch: agent-scope relaxed atomics
 // (coherent across XCDs, written through).
@@ -477,12 +476,13 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
       gemm(g, s);
     }
   };
-  // X = A22 V (A22 symmetric, lower stored).  Products of at least SYMM_SPLIT_ROWS
-  // rows split K over the pair buffer VW4, which is idle between a trailing update
-  // and the next pair's packing.  Smaller ones (all of a batch of orders <= 2048,
-  // whose instances already share the GPU) stay unsplit; the rule depends on the
-  // product alone, so a batched instance and a single solve of the same problem
-  // take the same path and give the same bits.
+  // X = A22 V (A22 symmetric, lower stored).  Products of at least split_rows
+  // rows (tuning table, by default 2048) split K over the pair buffer VW4, which
+  // is idle between a trailing update and the next pair's packing.  Smaller ones
+  // (all of a batch of orders <= 2048, whose instances already share the GPU) stay
+  // unsplit; the rule depends on the order alone, so a batched instance and a
+  // single solve of the same problem take the same path and give the same bits.
+  const int64_t split_rows = tune("symm_split_rows", N);
   auto symm_v = [&](int64_t col0, int w, int64_t n) {
     const int64_t p0 = col0 + b;
     Gemm g;
@@ -491,7 +491,7 @@ void sy2sb(const BandReduction& r, Arena& ws, hipStream_t s) {
     g.A = r.C + p0 + p0 * r.ldc; g.lda = r.ldc;
     g.B = r.C + p0 + col0 * r.ldc; g.ldb = r.ldc;
     g.C = X; g.ldc = n;
-    if (n >= SYMM_SPLIT_ROWS) {
+    if (n >= split_rows) {
       g.work = VW4;
       g.work_elems = (size_t)N * 4 * b;
     }

@@ -816,38 +816,80 @@ __device__ inline void vt_commit(const VTStage& f, double* Vs, double* Tt) {
   }
 }
 
+// The window of G column groups of 16: group g is lane & 15 of columns
+// col0 + 16 g (G = 2 shares every V / T operand read from LDS between the two
+// groups, and the groups' independent product chains fill each other's pipe
+// drains).  Z is read and written through a buffer descriptor over the wave's
+// 16 G columns: an element outside the matrix (a row past its end, a column past
+// the last one) gets an offset beyond the descriptor's range, so the hardware's
+// bounds check returns zero for the load and drops the store, with no branch and
+// only 32-bit offsets kept per lane.
+constexpr uint32_t OOB = 0x80000000u;
+
+template <int G>
 struct ZCol {
-  double* z;      // this lane's column of Z (row 0 of the matrix)
-  bool ok;        // column inside Z
-  int64_t base;   // matrix row of window row 0
-  int64_t nrel;   // window rows inside the matrix
+  // G = 1: this lane's column of Z (row 0) and whether it lies inside Z
+  double* z;
+  bool ok;
+  // G = 2: the wave's columns through a buffer descriptor
+  __amdgpu_buffer_rsrc_t rsrc;  // the wave's columns
+  uint32_t coff[G];             // byte offset of this lane's column in group g, or OOB
+  int64_t base;                 // matrix row of window row 0
+  int64_t nrel;                 // window rows inside the matrix
 };
 
-__device__ inline v4d z_load(const ZCol& zc, int64_t tile) {
-  const int l4 = (threadIdx.x & 63) >> 4;
+template <int G>
+__device__ inline uint32_t z_off(const ZCol<G>& zc, int g, int64_t tile, int r) {
+  const int64_t row = 16 * tile + ((threadIdx.x & 63) >> 4) + 4 * r;
+  return (zc.coff[g] != OOB && row < zc.nrel) ? zc.coff[g] + (uint32_t)((zc.base + row) * 8) : OOB;
+}
+
+template <int G>
+__device__ inline v4d z_load(const ZCol<G>& zc, int g, int64_t tile) {
   v4d v;
+  if constexpr (G == 1) {
+    const int l4 = (threadIdx.x & 63) >> 4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t row = 16 * tile + l4 + 4 * r;
-    v[r] = (zc.ok && row < zc.nrel) ? zc.z[zc.base + row] : 0.0;
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = 16 * tile + l4 + 4 * r;
+      v[r] = (zc.ok && row < zc.nrel) ? zc.z[zc.base + row] : 0.0;
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      v[r] = __builtin_bit_cast(
+          double, __builtin_amdgcn_raw_buffer_load_b64(zc.rsrc, z_off(zc, g, tile, r), 0, 0));
   }
   return v;
 }
 
-__device__ inline void z_store(const ZCol& zc, int64_t tile, const v4d& v) {
-  const int l4 = (threadIdx.x & 63) >> 4;
+template <int G>
+__device__ inline void z_store(const ZCol<G>& zc, int g, int64_t tile, const v4d& v) {
+  if constexpr (G == 1) {
+    const int l4 = (threadIdx.x & 63) >> 4;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t row = 16 * tile + l4 + 4 * r;
-    if (zc.ok && row < zc.nrel) zc.z[zc.base + row] = v[r];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = 16 * tile + l4 + 4 * r;
+      if (zc.ok && row < zc.nrel) zc.z[zc.base + row] = v[r];
+    }
+  } else {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      // the element goes through a scalar: this compiler's bit cast of a vector
+      // element taken by reference reads element 0 whatever the index
+      const double x = v[r];
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), zc.rsrc,
+                                            z_off(zc, g, tile, r), 0, 0);
+    }
   }
 }
 
 // One block on window slots S0 .. S0 + 5 (mod 8), V / T from LDS buffer cur; the
 // next block's V / T are fetched meanwhile and committed to the other buffer.
-template <int S0>
+template <int S0, int G>
 __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool upper, int64_t t,
-                                         v4d (&Z)[8], double (*Vs)[HP * VLD],
+                                         v4d (&Z)[G][8], double (*Vs)[HP * VLD],
                                          double (*Tt)[NBW * VLD], int& cur) {
   const int lane = threadIdx.x & 63, l15 = lane & 15, l4 = lane >> 4;
   int64_t gn = 0, tn = 0;
@@ -857,27 +899,48 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
   const double* V = Vs[cur];
   const double* Tb = Tt[cur];
   // W (32 x 16) = V^T Z: c tile 0 meets window tiles 0..4, c tile 1 tiles 1..5
-  v4d W0 = {0.0, 0.0, 0.0, 0.0}, W1 = {0.0, 0.0, 0.0, 0.0};
+  v4d W0[G], W1[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) W0[g] = W1[g] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int u = 0; u < 6; ++u) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const double* vr = V + (16 * u + 4 * r + l4) * VLD + l15;
-      if (u <= 4) W0 = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], Z[(S0 + u) & 7][r], W0, 0, 0, 0);
-      if (u >= 1) W1 = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], Z[(S0 + u) & 7][r], W1, 0, 0, 0);
+      if (u <= 4) {
+        const double v0 = vr[0];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          W0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, Z[g][(S0 + u) & 7][r], W0[g], 0, 0, 0);
+      }
+      if (u >= 1) {
+        const double v1 = vr[16];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          W1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, Z[g][(S0 + u) & 7][r], W1[g], 0, 0, 0);
+      }
     }
   }
-  W0 = -W0;
-  W1 = -W1;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    W0[g] = -W0[g];
+    W1[g] = -W1[g];
+  }
   // X = T (-W): T(c', c) = Tt[c][c'], zero for c' > c
-  v4d X0 = {0.0, 0.0, 0.0, 0.0}, X1 = {0.0, 0.0, 0.0, 0.0};
+  v4d X0[G], X1[G];
+#pragma unroll
+  for (int g = 0; g < G; ++g) X0[g] = X1[g] = v4d{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const double* t0 = Tb + (4 * r + l4) * VLD + l15;
     const double* t1 = Tb + (16 + 4 * r + l4) * VLD + l15;
-    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t0[0], W0[r], X0, 0, 0, 0);
-    X1 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[16], W1[r], X1, 0, 0, 0);
-    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[0], W1[r], X0, 0, 0, 0);
+    const double t00 = t0[0], t11 = t1[16], t10 = t1[0];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      X0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(t00, W0[g][r], X0[g], 0, 0, 0);
+      X1[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(t11, W1[g][r], X1[g], 0, 0, 0);
+      X0[g] = __builtin_amdgcn_mfma_f64_16x16x4f64(t10, W1[g][r], X0[g], 0, 0, 0);
+    }
   }
 
   // Z += V X: window tile u meets c tile 0 for u <= 4 and c tile 1 for u >= 1.
@@ -886,13 +949,19 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
   for (int r = 0; r < 4; ++r) {
 #pragma unroll
     for (int u = 0; u <= 4; ++u) {
-      const double* vr = V + (16 * u + l15) * VLD + 4 * r + l4;
-      Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[0], X0[r], Z[(S0 + u) & 7], 0, 0, 0);
+      const double v0 = V[(16 * u + l15) * VLD + 4 * r + l4];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        Z[g][(S0 + u) & 7] =
+            __builtin_amdgcn_mfma_f64_16x16x4f64(v0, X0[g][r], Z[g][(S0 + u) & 7], 0, 0, 0);
     }
 #pragma unroll
     for (int u = 1; u < 6; ++u) {
-      const double* vr = V + (16 * u + l15) * VLD + 4 * r + l4;
-      Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr[16], X1[r], Z[(S0 + u) & 7], 0, 0, 0);
+      const double v1 = V[(16 * u + l15) * VLD + 16 + 4 * r + l4];
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        Z[g][(S0 + u) & 7] =
+            __builtin_amdgcn_mfma_f64_16x16x4f64(v1, X1[g][r], Z[g][(S0 + u) & 7], 0, 0, 0);
     }
   }
   if (more) vt_commit(st, Vs[cur ^ 1], Tt[cur ^ 1]);
@@ -904,34 +973,57 @@ __device__ __forceinline__ void q2_block(const Q2Args& a, const Q2Pass& p, bool 
 // 4P .. 4P + 7 (mod 8).  Before the upper block, the four tiles it adds
 // (4t + 4 .. 4t + 7, prefetched into S) replace the tiles the previous lower
 // block finished; after the lower block, tiles 4t .. 4t + 3 are final.
-template <int P>
-__device__ __forceinline__ void q2_position(const Q2Args& a, const Q2Pass& p, const ZCol& zc,
-                                            int64_t t, v4d (&Z)[8], v4d (&S)[4],
+template <int P, int G>
+__device__ __forceinline__ void q2_position(const Q2Args& a, const Q2Pass& p, const ZCol<G>& zc,
+                                            int64_t t, v4d (&Z)[G][8], v4d (&S)[G][4],
                                             double (*Vs)[HP * VLD], double (*Tt)[NBW * VLD],
                                             int& cur) {
   constexpr int SL = (4 * P) & 7, SU = (4 * P + 2) & 7, SN = (4 * P + 4) & 7;
   if (t >= 1) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Z[(SN + i) & 7] = S[i];
+    for (int g = 0; g < G; ++g) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) S[i] = z_load(zc, 4 * t + 8 + i);
+      for (int i = 0; i < 4; ++i) Z[g][(SN + i) & 7] = S[g][i];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) S[g][i] = z_load(zc, g, 4 * t + 8 + i);
+    }
   }
-  if (p.two && t < p.Ph) q2_block<SU>(a, p, true, t, Z, Vs, Tt, cur);
-  q2_block<SL>(a, p, false, t, Z, Vs, Tt, cur);
+  if (p.two && t < p.Ph) q2_block<SU, G>(a, p, true, t, Z, Vs, Tt, cur);
+  q2_block<SL, G>(a, p, false, t, Z, Vs, Tt, cur);
 #pragma unroll
-  for (int i = 0; i < 4; ++i) z_store(zc, 4 * t + i, Z[(SL + i) & 7]);
+  for (int g = 0; g < G; ++g)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z_store(zc, g, 4 * t + i, Z[g][(SL + i) & 7]);
 }
 
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
-q2_apply_reg(Q2Args a) {
+// The whole Q2 application for the G column groups of each wave: 64 G columns
+// per workgroup of four waves.
+template <int G>
+__device__ __forceinline__ void q2_apply_reg_body(const Q2Args& a) {
   __shared__ double Vs[2][HP * VLD];
   __shared__ double Tt[2][NBW * VLD];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t col = (int64_t)blockIdx.x * RCOLS + wave * 16 + (lane & 15);
-  ZCol zc;
-  zc.ok = col < a.ncols;
-  zc.z = a.Z + (zc.ok ? col : 0) * a.ldz;
+  ZCol<G> zc;
+  {
+    const int64_t col = (int64_t)blockIdx.x * RCOLS + wave * 16 + (lane & 15);
+    zc.ok = col < a.ncols;
+    zc.z = a.Z + (zc.ok ? col : 0) * a.ldz;
+  }
+  if constexpr (G > 1) {
+    const int64_t wcol = (int64_t)blockIdx.x * (RCOLS * G) + wave * (16 * G);
+    int64_t nw = a.ncols - wcol;  // columns of this wave inside Z
+    if (nw > 16 * G) nw = 16 * G;
+    if (nw < 0) nw = 0;
+    const int64_t bytes = nw > 0 ? ((nw - 1) * a.ldz + a.n) * 8 : 0;
+    zc.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.Z + (nw > 0 ? wcol : 0) * a.ldz, (short)0,
+                                                (int)bytes, 0x00020000);
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int c = 16 * g + (lane & 15);
+      zc.coff[g] = c < nw ? (uint32_t)(c * a.ldz * 8) : OOB;
+    }
+  }
   if (a.ngroups <= 0) return;
   int cur = 0;
   {
@@ -941,28 +1033,48 @@ q2_apply_reg(Q2Args a) {
     vt_commit(st, Vs[0], Tt[0]);
   }
   __syncthreads();
-  v4d Z[8], S[4];
+  v4d Z[G][8], S[G][4];
   for (int64_t jh = a.ngroups - 1; jh >= 0; jh -= 2) {
     const Q2Pass p = q2_pass(a, jh);
     zc.base = p.base;
     zc.nrel = p.nrel;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) Z[s] = z_load(zc, s);
+    for (int g = 0; g < G; ++g) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) S[i] = z_load(zc, 8 + i);
+      for (int s = 0; s < 8; ++s) Z[g][s] = z_load(zc, g, s);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) S[g][i] = z_load(zc, g, 8 + i);
+    }
     for (int64_t t = 0; t < p.Pl; t += 2) {
-      q2_position<0>(a, p, zc, t, Z, S, Vs, Tt, cur);
-      if (t + 1 < p.Pl) q2_position<1>(a, p, zc, t + 1, Z, S, Vs, Tt, cur);
+      q2_position<0, G>(a, p, zc, t, Z, S, Vs, Tt, cur);
+      if (t + 1 < p.Pl) q2_position<1, G>(a, p, zc, t + 1, Z, S, Vs, Tt, cur);
     }
     // the four tiles loaded last, 4 Pl .. 4 Pl + 3
-    if ((p.Pl & 1) == 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) z_store(zc, 4 * p.Pl + i, Z[i]);
-    } else {
+    for (int g = 0; g < G; ++g) {
+      if ((p.Pl & 1) == 0) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) z_store(zc, 4 * p.Pl + i, Z[4 + i]);
+        for (int i = 0; i < 4; ++i) z_store(zc, g, 4 * p.Pl + i, Z[g][i]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) z_store(zc, g, 4 * p.Pl + i, Z[g][4 + i]);
+      }
     }
   }
+}
+
+// One column group per wave, two waves per SIMD (two workgroups per CU): for
+// column counts that would leave CUs idle with 128 columns per workgroup.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+q2_apply_reg(Q2Args a) {
+  q2_apply_reg_body<1>(a);
+}
+
+// Two column groups per wave, one wave per SIMD: the full register file (no
+// spills) and twice the independent MFMA chains per wave.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
+q2_apply_reg2(Q2Args a) {
+  q2_apply_reg_body<2>(a);
 }
 
 }  // namespace
@@ -988,7 +1100,13 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
   {
     // algorithmic flops: ~n^2 / (2b) reflectors of length b, 4b flops per column each
     ProbeScope probe(PROBE_Q2_APPLY, s, 2.0 * (double)n * (double)n * (double)ncols);
-    if (c.b == 64)
+    // the register-window kernels address a wave's 16 or 32 columns of Z with
+    // 32-bit byte offsets
+    if (c.b == 64 && (32 * ldz + n) * 8 >= (int64_t)OOB)
+      throw HipError{hipErrorInvalidValue, "leading dimension of Z too large"};
+    if (c.b == 64 && ncols >= tune("q2_wide_min_cols", n))
+      hipLaunchKernelGGL(q2_apply_reg2, dim3((unsigned)cdiv(ncols, 2 * RCOLS)), dim3(NT), 0, s, a);
+    else if (c.b == 64)
       hipLaunchKernelGGL(q2_apply_reg, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
     else
       hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
@@ -1029,7 +1147,7 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     // a sweep's positions are ever worked on at once: more workgroups would only
     // spin (and, in batched solves, keep other instances' chases off the CUs).
     const int64_t npos0 = (n - 2) / c.b + 1;
-    int64_t groups = npos0 / 2 + 8;
+    int64_t groups = npos0 / 2 + tune("chase_extra_groups", n);
     if (groups > nsweeps) groups = nsweeps;
     if (groups > 512) groups = 512;
     ProbeScope probe(PROBE_CHASE, s, 6.0 * c.b * (double)n * (double)n);

@@ -155,6 +155,9 @@ bool force_wait_timeout();
 // non-convergence (info = its first index + 1), as a real failure would.
 void set_force_eig_failure(bool on);
 bool force_eig_failure();
+// Tuned parameter `key` for order M: a run-time override, else the tuning
+// table's entry, else the built-in rule (tune.hip lists the keys).
+int64_t tune(const char* key, int64_t M);
 // Wall-clock ticks a bounded wait may last before it gives up (10 s).
 uint64_t wait_limit_ticks();
 

@@ -69,6 +69,7 @@ struct Work {
   double* lamw;   // eigenvalues being merged (n)
   MergeInfo* info;  // per merge
   GemmDesc* desc;   // 2 per merge
+  double* flops;    // merge products' flops, summed over the levels (1)
   double* G;      // n x n
   double* U;      // n x n
   double* Out;    // n x n
@@ -635,9 +636,13 @@ __global__ void bisect_dev(int64_t n, const double* __restrict__ d, const double
   lam[k] = 0.5 * (a + b);
 }
 
+// Leaves hold at most `dc_leaf` (tuning table, 8 .. LEAF) rows.
 int tree_depth(int64_t n) {
+  int64_t leaf = tune("dc_leaf", n);
+  if (leaf < 8) leaf = 8;
+  if (leaf > LEAF) leaf = LEAF;
   int D = 0;
-  while (cdiv(n, (int64_t)1 << D) > LEAF) ++D;
+  while (cdiv(n, (int64_t)1 << D) > leaf) ++D;
   return D;
 }
 
@@ -665,6 +670,7 @@ Work carve(Arena& ws, int64_t n) {
   w.lamw = ws.take<double>(n);
   w.info = ws.take<MergeInfo>(maxm);
   w.desc = ws.take<GemmDesc>(2 * maxm);
+  w.flops = ws.take<double>(1);
   if (D > 0) {
     w.G = ws.take<double>((size_t)n * n);
     w.U = ws.take<double>((size_t)n * n);
@@ -681,6 +687,19 @@ namespace {
 
 constexpr int64_t HOST_SIZED_MIN = 8192;
 constexpr unsigned HOST_SIZED_MAX_P = 4;  // merges per level (top three levels)
+
+// flops += 2 m n k over a level's merge products (their sizes after deflation
+// live on the device).  One workgroup; levels are added in order.
+__global__ void __launch_bounds__(64) sum_merge_flops(const GemmDesc* __restrict__ desc, int count,
+                                                      double* flops) {
+  double f = 0.0;
+  for (int i = threadIdx.x; i < count; i += 64) {
+    const GemmDesc d = desc[i];
+    if (d.m > 0 && d.n > 0 && d.k > 0) f += 2.0 * (double)d.m * (double)d.n * (double)d.k;
+  }
+  for (int off = 32; off > 0; off >>= 1) f += __shfl_xor(f, off, 64);
+  if (threadIdx.x == 0) *flops += f;
+}
 
 bool fast_aligned(const GemmDesc& d) {
   return (uintptr_t)d.A % 16 == 0 && (uintptr_t)d.B % 16 == 0 && d.lda % 2 == 0 && d.ldb % 2 == 0;
@@ -733,9 +752,10 @@ size_t stedc_workspace(int64_t n) {
 }
 
 void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, int64_t ldz,
-           int32_t* info, Arena& ws, hipStream_t s) {
+           int32_t* info, Arena& ws, hipStream_t s, double* flops_host) {
   if (n <= 0) return;
   Work w = carve(ws, n);
+  if (flops_host) fill_f64(w.flops, 1, 0.0, s);
   const int D = tree_depth(n);
   // The top merges' GEMMs dominate large orders.  Their sizes depend on deflation
   // and live on the device; for an order >= HOST_SIZED_MIN on a stream that is not
@@ -777,6 +797,11 @@ void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, 
     hipLaunchKernelGGL(merge_gather, dim3((unsigned)Nmax, P), dim3(256), 0, s, n, t, w,
                        (const double*)Z, ldz);
     GEP_LAUNCH_CHECK();
+    if (flops_host) {
+      hipLaunchKernelGGL(sum_merge_flops, dim3(1), dim3(64), 0, s, (const GemmDesc*)w.desc,
+                         (int)(2 * P), w.flops);
+      GEP_LAUNCH_CHECK();
+    }
     if (host_sized && P <= HOST_SIZED_MAX_P)
       merge_gemms_host(w.desc, (int)(2 * P), s);
     else
@@ -784,6 +809,8 @@ void stedc(int64_t n, const double* d, const double* e, double* lam, double* Z, 
     hipLaunchKernelGGL(merge_scatter, dim3((unsigned)Nmax, P), dim3(256), 0, s, n, t, w, lam, Z, ldz);
     GEP_LAUNCH_CHECK();
   }
+  if (flops_host)
+    GEP_HIP(hipMemcpyAsync(flops_host, w.flops, sizeof(double), hipMemcpyDeviceToHost, s));
 }
 
 void stebz_ws(int64_t n, const double* d, const double* e, double* lam, double* bounds2,

@@ -78,8 +78,10 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
 size_t stedc_workspace(int64_t n);
 // Eigenvalues (ascending) and eigenvectors of the symmetric tridiagonal (d, e).
 // d, e are read only.  info: set to k > 0 if a secular equation failed.
+// flops_host (optional, pinned host memory): receives, asynchronously, the merge
+// products' flops (2 m n k summed after deflation).
 void stedc(int64_t n, const double* d, const double* e, double* lambda, double* Z, int64_t ldz,
-           int32_t* info, Arena& ws, hipStream_t s);
+           int32_t* info, Arena& ws, hipStream_t s, double* flops_host = nullptr);
 // Eigenvalues only, by bisection; bounds2 is 2 doubles of device scratch.
 void stebz_ws(int64_t n, const double* d, const double* e, double* lambda, double* bounds2,
               hipStream_t s);

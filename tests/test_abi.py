@@ -225,3 +225,41 @@ def test_solve_explicit_inverse_workspace(lib):
     assert lib.gep_workspace_size_explicit_inverse(0) == 256
     need = lib.gep_workspace_size_explicit_inverse(M)
     assert _explicit(lib, M, wsb=need - 1) == -2
+
+
+def test_tuning_table_api(lib, tmp_path):
+    """The tuning table's host logic: built-in rules, overrides (latest covering
+    override wins), range and value checks, loading a file and rejecting a
+    malformed one (the previous table stays), clearing."""
+    get = lambda k, M: lib.gep_tune_get(k.encode(), M)
+    lib.gep_tune_clear()
+    assert [get("band_width", M) for M in (100, 256, 2047, 2048)] == [16, 32, 32, 64]
+    assert get("dc_leaf", 1000) == 64 and get("symm_split_rows", 10) == 2048
+    assert get("no_such_parameter", 10) == -1
+    assert lib.gep_tune_set(b"band_width", 100, 200, 24) == 0
+    assert lib.gep_tune_set(b"band_width", 150, 160, 48) == 0
+    assert (get("band_width", 99), get("band_width", 100), get("band_width", 155)) == (16, 24, 48)
+    assert lib.gep_tune_set(b"band_width", 0, 10, 65) == -1      # value out of range
+    assert lib.gep_tune_set(b"band_width", 10, 9, 16) == -1      # empty range
+    assert lib.gep_tune_set(b"bogus", 0, 10, 16) == -1
+    assert lib.gep_tune_set(None, 0, 10, 16) == -1
+    lib.gep_tune_reset_overrides()
+    assert get("band_width", 155) == 16
+    good = tmp_path / "t.json"
+    good.write_text('{"device": "x", "parameters": {"band_width": [{"m_lo": 64, "m_hi": 127, '
+                    '"value": 24, "ms": 1.5}], "dc_leaf": [{"m_lo": 0, "m_hi": 9999, "value": 32}],'
+                    ' "future_parameter": [{"m_lo": 0, "m_hi": 1, "value": 1}]}, "timings": []}')
+    assert lib.gep_tune_load(str(good).encode()) == 2
+    assert (get("band_width", 100), get("band_width", 300), get("dc_leaf", 5000)) == (24, 32, 32)
+    bad = tmp_path / "bad.json"
+    for text in ('{"parameters": {"band_width": [{"m_lo": 1, "m_hi": 2, "value": 99}]}}',
+                 '{"parameters": {"band_width": [{"m_lo": 1, "value": 16}]}}',
+                 '{"parameters": {"band_width": [{"m_lo": 1.5, "m_hi": 2, "value": 16}]}}',
+                 '{"parameters": ', '[1, 2]'):
+        bad.write_text(text)
+        assert lib.gep_tune_load(str(bad).encode()) == -1, text
+        assert get("band_width", 100) == 24  # previous table kept
+    assert lib.gep_tune_load(str(tmp_path / "missing.json").encode()) == -1
+    lib.gep_tune_clear()
+    assert get("band_width", 100) == 16
+    lib.gep_tune_load(None)  # back to the default location (the committed table, if any)

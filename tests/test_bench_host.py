@@ -16,16 +16,24 @@ import bench  # noqa: E402
 
 @pytest.mark.parametrize("M", [1, 255, 256, 2047, 2048, 32768])
 def test_alg_flops_closed_form(M):
-    # (23/3) M^3 + 6 b M^2: R1 M^3/3, R2-4 M^3, S1 4M^3/3, S4 2M^3, S5 2M^3, R5 M^3,
-    # S2 6bM^2 (the D&C's deflation-dependent flops are not counted)
-    b = 64 if M >= 2048 else (32 if M >= 256 else 16)
-    assert bench.band_width(M) == b
-    assert bench.alg_flops(M) == pytest.approx(23.0 / 3.0 * M ** 3 + 6.0 * b * M ** 2, rel=1e-12)
+    # (23/3) M^3 + 6 b M^2 + F_D&C: R1 M^3/3, R2-4 M^3, S1 4M^3/3, S4 2M^3, S5 2M^3,
+    # R5 M^3, S2 6bM^2, and the divide and conquer's measured merge flops
+    for b in (16, 32, 64):
+        assert bench.alg_flops(M, b) == pytest.approx(23.0 / 3.0 * M ** 3 + 6.0 * b * M ** 2,
+                                                      rel=1e-12)
+        assert bench.alg_flops(M, b, 1.5e9) == pytest.approx(bench.alg_flops(M, b) + 1.5e9)
+
+
+def test_band_width_is_the_library_value():
+    from paper_1504_06443_amd import _binding
+    L = _binding.lib()
+    for M in (100, 300, 1000, 3000, 32768):
+        assert bench.band_width(M) == L.gep_tune_get(b"band_width", M)
 
 
 def test_alg_flops_at_the_benchmark_size():
-    # 2.70e14 at M = 32768 (b = 64)
-    assert bench.alg_flops(32768) == pytest.approx(2.7016e14, rel=1e-4)
+    # 2.70e14 at M = 32768 (b = 64), before the divide and conquer's merge flops
+    assert bench.alg_flops(32768, 64) == pytest.approx(2.7016e14, rel=1e-4)
 
 
 def test_kernel_traffic_matches_the_committed_summary():

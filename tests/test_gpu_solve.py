@@ -302,3 +302,56 @@ def test_sign_convention_matches_oracle(gpu, M):
         assert c > 1.0 - 1e-8, (j, c)
         compared += 1
     assert compared >= M // 2, compared
+
+
+def _tune(key, lo, hi, value):
+    from paper_1504_06443_amd import _binding
+    assert _binding.lib().gep_tune_set(key.encode(), lo, hi, value) == 0
+
+
+def _tune_reset():
+    from paper_1504_06443_amd import _binding
+    _binding.lib().gep_tune_reset_overrides()
+
+
+@pytest.mark.parametrize("M", [2080, 2113, 3001])
+def test_solve_band64_wide_q2(gpu, M):
+    """The Q2 back transformation with two 16-column groups per wave (one wave per
+    SIMD), which the built-in rule keeps for 128 columns per compute unit and
+    more, forced on at ragged orders: a partial last workgroup, waves whose
+    columns run past the matrix, odd numbers of sweep groups (M = 2080).  Checked
+    like the band-64 orders above, and against the default kernel's eigenvalues."""
+    say(f"[solve] band 64, Q2 32 columns per wave, M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 500 + M)
+    lam0, Y0 = _gep().solve(to_gpu(A), to_gpu(B))
+    _tune("q2_wide_min_cols", M, M, 0)
+    try:
+        lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    finally:
+        _tune_reset()
+    lam, Y = to_np(lam), to_np(Y)
+    n1 = np.abs(A).sum(axis=0).max()
+    assert np.abs(lam - to_np(lam0)).max() <= 1e-13 * n1
+    orth = np.abs(Y.T @ B @ Y - np.eye(M)).max()
+    assert orth <= TOL_ORTH, orth
+    res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+    assert res <= TOL_RES, res
+    worst = max_subspace_sine(Y, to_np(Y0), B, to_np(lam0), 1e-8 * n1)
+    assert worst <= 1e-11 * n1, worst
+
+
+@pytest.mark.parametrize("key,value", [("band_width", 8), ("band_width", 24), ("band_width", 48),
+                                       ("band_width", 64), ("dc_leaf", 16), ("dc_leaf", 40),
+                                       ("chase_extra_groups", 0), ("symm_split_rows", 64)])
+def test_solve_tuned_parameters(gpu, key, value):
+    """Every admissible value of a tuning-table parameter gives a correct solve:
+    M = 600 against the oracle with one parameter overridden."""
+    M = 600
+    say(f"[solve] tuned {key}={value} M={M}")
+    A, B = synth.banded_pair(M, 8.0, 4242)
+    _tune(key, M, M, value)
+    try:
+        lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+    finally:
+        _tune_reset()
+    check_against_oracle(A, B, to_np(lam), to_np(Y))
