@@ -70,6 +70,8 @@ def lib():
         L.orc_bisect_all.restype = None
         L.orc_tql.argtypes = [I, P, P, P, I]
         L.orc_tql.restype = I
+        L.orc_ldlt_inertia.argtypes = [I, P, I]
+        L.orc_ldlt_inertia.restype = I
         _lib = L
     return _lib
 
@@ -239,13 +241,12 @@ def inertia_count(A, B, sigma: float) -> int:
     B is positive definite, so A - sigma B is congruent to C - sigma I with
     C = L^{-1} A L^{-T} (Eq. 5), and by Sylvester's law of inertia the number of
     negative eigenvalues of A - sigma B is #{lambda_k < sigma}.  That number is
-    read off a symmetric indefinite factorisation P (A - sigma B) P^T = U D U^T
-    (LAPACK dsytrf, Bunch-Kaufman pivoting: a library step) as the number of
-    negative eigenvalues of the block-diagonal D (1 x 1 pivots by sign, 2 x 2
-    pivots [a b; b c] by determinant and trace).  Only the lower triangles of A
-    and B are read; the work array may overwrite nothing the caller holds.
+    read off a symmetric indefinite factorisation of A - sigma B with diagonal
+    pivoting (orc_ldlt_inertia: Bunch-Kaufman, plain C) as the number of negative
+    eigenvalues of its block-diagonal factor.  Only the lower triangles of A and
+    B are read.  Raises ValueError when a pivot is exactly singular (sigma is an
+    eigenvalue).
     """
-    from scipy.linalg import lapack
     A = np.asarray(A, dtype=np.float64)
     B = np.asarray(B, dtype=np.float64)
     n = A.shape[0]
@@ -258,24 +259,10 @@ def inertia_count(A, B, sigma: float) -> int:
     for j0 in range(0, n, step):
         j1 = min(n, j0 + step)
         W[:, j0:j1] = np.tril(A[:, j0:j1], -j0) - sigma * np.tril(B[:, j0:j1], -j0)
-    lu, ipiv, info = lapack.dsytrf(W, lower=1, overwrite_a=1)
-    if info < 0:
-        raise ValueError(f"dsytrf argument {-info}")
-    neg = 0
-    k = 0
-    while k < n:
-        if ipiv[k] > 0:  # 1 x 1 pivot
-            neg += lu[k, k] < 0.0
-            k += 1
-        else:  # 2 x 2 pivot in rows / columns k, k+1 (lower storage)
-            a, b, c = lu[k, k], lu[k + 1, k], lu[k + 1, k + 1]
-            det = a * c - b * b
-            if det < 0.0:
-                neg += 1
-            elif a + c < 0.0:
-                neg += 2
-            k += 2
-    return int(neg)
+    neg = int(lib().orc_ldlt_inertia(n, _ptr(W), n))
+    if neg < 0:
+        raise ValueError("A - sigma B is singular: sigma is an eigenvalue")
+    return neg
 
 
 def eigvals(A, B) -> np.ndarray:

@@ -349,3 +349,92 @@ int64_t orc_tql(int64_t n, double *d, double *e_in, double *z, int64_t ldz) {
     free(sn);
     return fail;
 }
+
+/*
+ * Number of negative eigenvalues of the symmetric matrix whose lower triangle is
+ * in a (n x n, ld; destroyed), from a symmetric indefinite factorisation
+ * P a P^T = L D L^T with diagonal pivoting (Bunch-Kaufman, Golub and Van Loan,
+ * "Matrix Computations", section 4.4): D is block diagonal with 1 x 1 and 2 x 2
+ * blocks, and by Sylvester's law of inertia a has as many negative eigenvalues as
+ * D (a 1 x 1 block by its sign; a 2 x 2 block one if its determinant is negative,
+ * two if it is positive with a negative trace).  Only D's blocks are needed, so L
+ * is not kept.  Returns -1 if an exactly singular pivot occurs.
+ */
+static void sym_swap_lower(int64_t n, double *a, int64_t ld, int64_t k, int64_t kk, int64_t p) {
+    /* swap rows/columns kk < p of the trailing part (indices >= k), lower storage */
+    double t;
+    t = AT(a, kk, kk, ld); AT(a, kk, kk, ld) = AT(a, p, p, ld); AT(a, p, p, ld) = t;
+    for (int64_t j = k; j < kk; ++j) {
+        t = AT(a, kk, j, ld); AT(a, kk, j, ld) = AT(a, p, j, ld); AT(a, p, j, ld) = t;
+    }
+    for (int64_t i = kk + 1; i < p; ++i) {
+        t = AT(a, i, kk, ld); AT(a, i, kk, ld) = AT(a, p, i, ld); AT(a, p, i, ld) = t;
+    }
+    for (int64_t i = p + 1; i < n; ++i) {
+        t = AT(a, i, kk, ld); AT(a, i, kk, ld) = AT(a, i, p, ld); AT(a, i, p, ld) = t;
+    }
+}
+
+int64_t orc_ldlt_inertia(int64_t n, double *a, int64_t ld) {
+    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+    int64_t neg = 0, k = 0;
+    while (k < n) {
+        const double akk = fabs(AT(a, k, k, ld));
+        int64_t r = k;
+        double colmax = 0.0;
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(AT(a, i, k, ld)) > colmax) {
+                colmax = fabs(AT(a, i, k, ld));
+                r = i;
+            }
+        if (akk == 0.0 && colmax == 0.0) return -1;
+        int size = 1;
+        int64_t piv = k;
+        if (!(akk >= alpha * colmax)) {
+            double rowmax = 0.0;
+            for (int64_t j = k; j < r; ++j)
+                if (fabs(AT(a, r, j, ld)) > rowmax) rowmax = fabs(AT(a, r, j, ld));
+            for (int64_t i = r + 1; i < n; ++i)
+                if (fabs(AT(a, i, r, ld)) > rowmax) rowmax = fabs(AT(a, i, r, ld));
+            if (akk * rowmax >= alpha * colmax * colmax) {
+                piv = k;
+            } else if (fabs(AT(a, r, r, ld)) >= alpha * rowmax) {
+                piv = r;
+            } else {
+                size = 2;
+                piv = r;
+            }
+        }
+        const int64_t kk = (size == 1) ? k : k + 1;
+        if (piv != kk) sym_swap_lower(n, a, ld, k, kk, piv);
+        if (size == 1) {
+            const double d = AT(a, k, k, ld);
+            if (d == 0.0) return -1;
+            if (d < 0.0) ++neg;
+            /* trailing lower triangle -= l l^T d, l = a(k+1:, k) / d */
+#pragma omp parallel for schedule(dynamic, 16) if (n - k > 256)
+            for (int64_t j = k + 1; j < n; ++j) {
+                const double f = AT(a, j, k, ld) / d;
+                for (int64_t i = j; i < n; ++i) AT(a, i, j, ld) -= AT(a, i, k, ld) * f;
+            }
+            k += 1;
+        } else {
+            const double d11 = AT(a, k, k, ld), d21 = AT(a, k + 1, k, ld), d22 = AT(a, k + 1, k + 1, ld);
+            const double det = d11 * d22 - d21 * d21;
+            if (det == 0.0) return -1;
+            if (det < 0.0) neg += 1;
+            else if (d11 + d22 < 0.0) neg += 2;
+            /* trailing -= [a_k a_k1] D^{-1} [a_k a_k1]^T */
+            const double e11 = d22 / det, e21 = -d21 / det, e22 = d11 / det;
+#pragma omp parallel for schedule(dynamic, 16) if (n - k > 256)
+            for (int64_t j = k + 2; j < n; ++j) {
+                const double xj = AT(a, j, k, ld), yj = AT(a, j, k + 1, ld);
+                const double fj = e11 * xj + e21 * yj, gj = e21 * xj + e22 * yj;
+                for (int64_t i = j; i < n; ++i)
+                    AT(a, i, j, ld) -= AT(a, i, k, ld) * fj + AT(a, i, k + 1, ld) * gj;
+            }
+            k += 2;
+        }
+    }
+    return neg;
+}

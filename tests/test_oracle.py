@@ -378,3 +378,61 @@ def test_inertia_count_matches_eigenvalues():
     assert oracle.inertia_count(J, np.eye(80), 0.0) == 40
     assert oracle.inertia_count(J, np.eye(80), -1.5) == 0
     assert oracle.inertia_count(J, np.eye(80), 1.5) == 80
+
+
+def test_inertia_count_pivot_cases_against_numpy():
+    """The oracle's own indefinite factorisation against LAPACK's symmetric
+    eigenvalue count (numpy.linalg.eigvalsh) on matrices that exercise each pivot
+    choice: dominant diagonal (1 x 1 in place), zero or tiny diagonal with large
+    off-diagonal (2 x 2 blocks), a large entry far below the diagonal (row and
+    column interchanges), a 2 x 2 block with positive determinant and negative
+    trace, and an exactly singular pivot (ValueError)."""
+    rng = np.random.default_rng(4242)
+    cases = []
+    for n in (3, 8, 33, 120, 301):
+        X = rng.standard_normal((n, n))
+        cases.append(0.5 * (X + X.T))                      # generic indefinite
+        Z = 0.5 * (X + X.T)
+        np.fill_diagonal(Z, 0.0)
+        cases.append(Z)                                     # zero diagonal
+        D = Z.copy()
+        np.fill_diagonal(D, 1e-8 * rng.standard_normal(n))
+        D[n - 1, 0] = D[0, n - 1] = 50.0                    # far pivot row
+        cases.append(D)
+        T = np.diag(rng.uniform(1, 2, n) * rng.choice([-1.0, 1.0], n))
+        cases.append(T + 1e-3 * Z)                          # 1 x 1 pivots
+    # 2 x 2 blocks with det > 0, trace < 0: [[-1, 0.5], [0.5, -1]] inside zero diagonal
+    K = np.kron(np.eye(20), np.array([[-0.01, 3.0], [3.0, -0.02]]))
+    cases.append(K)
+    for S in cases:
+        n = S.shape[0]
+        w = np.linalg.eigvalsh(S)
+        gap = np.min(np.abs(w))
+        assert gap > 1e-10, "case must be nonsingular"
+        assert oracle.inertia_count(S, np.eye(n), 0.0) == int((w < 0).sum())
+        # a shift between two eigenvalues, B a general SPD matrix
+        _, Bs = synth.banded_pair(n, 2.0, 7 + n)
+        lam = np.linalg.eigvalsh(np.linalg.solve(np.linalg.cholesky(Bs), np.linalg.solve(
+            np.linalg.cholesky(Bs), S).T))
+        k = n // 2
+        if k > 0 and lam[k] - lam[k - 1] > 1e-8:
+            assert oracle.inertia_count(S, Bs, 0.5 * (lam[k - 1] + lam[k])) == k
+    with pytest.raises(ValueError):
+        oracle.inertia_count(np.zeros((4, 4)), np.eye(4), 0.0)
+
+
+@pytest.mark.parametrize("name", ["m8192", "m32768"])
+def test_stored_eigenvalues_agree_with_stored_inertia(name):
+    """The two stored references of a workload come from independent routes of the
+    oracle (bisection on the tridiagonal matrix for the eigenvalues; a symmetric
+    indefinite factorisation of A - sigma B for the counts): the number of stored
+    eigenvalues below each shift must equal the stored count."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    pe, pc = os.path.join(here, f"{name}_eigenvalues.npy"), os.path.join(here, f"{name}_inertia.json")
+    if not (os.path.exists(pe) and os.path.exists(pc)):
+        pytest.skip(f"{name}: stored eigenvalues or counts not present")
+    lam = np.load(pe)
+    for s, c in json.load(open(pc))["counts_below_sigma"].items():
+        assert int(np.count_nonzero(lam < float(s))) == c, s
