@@ -187,6 +187,31 @@ int gep_solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const do
                                void* workspace, size_t ws_bytes, int32_t* info, void* stream);
 
 /*
+ * Block Jacobi SEP solver behind the reducer: the combination the paper's outlook
+ * proposes (section 6: a solver of a different mathematical foundation that only
+ * handles standard problems, made usable for generalized ones by the reducer).
+ * B = L L^T and C = L^{-1} A L^{-T} as in gep_solve (Eqs. 4-5); the eigenpairs of
+ * C by parallel two-sided block Jacobi (32-row blocks, all disjoint block pairs
+ * of a round at once: each 64 x 64 pair matrix diagonalised exactly in LDS, the
+ * rotations applied to C and to the eigenvector matrix on the matrix cores) until
+ * the off-diagonal norm is at rounding level; Y = L^{-T} Z (Eq. 6).  No band or
+ * tridiagonal form is formed.  About 12 M^3 flops per sweep, 6-10 sweeps: several
+ * times the work of gep_solve, which it does not replace; the stream is
+ * synchronised once per sweep (convergence test), so the call cannot be captured
+ * in a graph.
+ *   A, B, lda, ldb, lambda, Y, ldy: as gep_solve with job = GEP_JOB_VECTORS (FP64).
+ *   workspace: >= gep_workspace_size_jacobi(M) bytes, 256-byte aligned.
+ *   info: as gep_solve, with k = M when the sweeps have not converged after 30.
+ * gep_last_jacobi_sweeps: sweeps of the last gep_solve_jacobi on this process.
+ * Argument errors name the argument by its position (1 = M ... 11 = info).
+ */
+size_t gep_workspace_size_jacobi(int64_t M);
+int gep_solve_jacobi(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double* lambda, double* Y, int64_t ldy, void* workspace, size_t ws_bytes,
+                     int32_t* info, void* stream);
+int gep_last_jacobi_sweeps(void);
+
+/*
  * Many independent problems of different orders in one call (the k-point-like
  * batches of electronic-structure codes; the paper solves one problem per run).
  * Arrays ending in _host are HOST arrays of length `batch` (orders, leading
@@ -194,8 +219,11 @@ int gep_solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const do
  * info is a DEVICE int32 array [batch], one LAPACK-style code per instance.
  * The instances are spread over worker streams forked from `stream` with events
  * (largest first, each to the least loaded stream) and joined back into it, so
- * the call can be captured in a HIP graph and replayed.  Workspace:
- * gep_workspace_size_batched bytes for the same M_host list.
+ * the call can be captured in a HIP graph and replayed.  Outside capture each
+ * worker stream's instances are enqueued by a host thread of its own (the
+ * launches and their order per stream are the same as from one thread, and so
+ * are the results; gep_batched_threads(0) enqueues from the calling thread
+ * only).  Workspace: gep_workspace_size_batched bytes for the same M_host list.
  */
 size_t gep_workspace_size_batched(int batch, const int64_t* M_host, int job, int prec);
 int gep_solve_batched(int batch, const int64_t* M_host, const double* const* A_host,
@@ -203,6 +231,9 @@ int gep_solve_batched(int batch, const int64_t* M_host, const double* const* A_h
                       const int64_t* ldb_host, double* const* lambda_host, double* const* Y_host,
                       const int64_t* ldy_host, int job, int prec, void* workspace, size_t ws_bytes,
                       int32_t* info, void* stream);
+/* Enqueue batched solves from one host thread per worker stream (1, the
+ * default) or from the calling thread only (0); process-wide.  Returns GEP_OK. */
+int gep_batched_threads(int on);
 
 /*
  * Phase entry points (same conventions).  They expose the steps of gep_solve one
@@ -335,7 +366,10 @@ const char* gep_probe_name(int kernel);
  *   symm_split_rows     the band reduction's symmetric products split their sum
  *                       over workgroups from this many rows (>= 1; 2048);
  *   chase_extra_groups  bulge chase workgroups beyond half the first sweep's
- *                       positions (0..512; 8).
+ *                       positions (0..512; 8);
+ *   q2_mixed_fp32       GEP_PREC_MIXED: the Q2 back transformation in FP32
+ *                       arithmetic on the matrix cores (1) or in FP64 (0; built
+ *                       in: 0, measured faster at M = 32768).
  * Results depend on band_width and dc_leaf only through rounding; every
  * parameter value gives a correct solve.  A batched instance and a single solve
  * of the same order use the same values.

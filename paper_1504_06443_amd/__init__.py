@@ -20,13 +20,14 @@ import os
 from ._binding import (GEPError, JOB_VALUES, JOB_VECTORS, PREC_FP64, PREC_MIXED, lib, lib_path,
                        workspace_size)
 from .api import (BatchedGraph, BatchedSolver, GEPFunction, band_reduce, backward, dgemm, reduce,
-                  solve, solve_batched, solve_cholfree, solve_explicit_inverse, solve_lowest, tridiag_eig, tridiagonalize, profile_enable, profile_read, PHASES, PROBE_KERNELS,
+                  solve, solve_batched, solve_cholfree, solve_explicit_inverse, solve_jacobi, solve_lowest, tridiag_eig, tridiagonalize, profile_enable, profile_read, PHASES, PROBE_KERNELS,
                   probe_enable, probe_read)
 
 __all__ = [
     "GEPError", "JOB_VALUES", "JOB_VECTORS", "PREC_FP64", "PREC_MIXED", "lib", "lib_path",
     "workspace_size", "BatchedGraph", "BatchedSolver", "GEPFunction", "band_reduce", "backward",
-    "dgemm", "reduce", "solve", "solve_cholfree", "solve_explicit_inverse", "solve_lowest",
+    "dgemm", "reduce", "solve", "solve_cholfree", "solve_explicit_inverse", "solve_jacobi",
+    "solve_lowest",
     "solve_batched", "tridiag_eig", "tridiagonalize", "profile_enable", "profile_read", "PHASES",
     "PROBE_KERNELS", "probe_enable", "probe_read",
 ]

@@ -59,8 +59,12 @@ SIGNATURES = {
     "gep_solve_cholfree": (INT, [I64, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
     "gep_workspace_size_explicit_inverse": (SZ, [I64]),
     "gep_solve_explicit_inverse": (INT, [I64, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
+    "gep_workspace_size_jacobi": (SZ, [I64]),
+    "gep_solve_jacobi": (INT, [I64, P, I64, P, I64, P, P, I64, P, SZ, P, P]),
+    "gep_last_jacobi_sweeps": (INT, []),
     "gep_workspace_size_batched": (SZ, [INT, P, INT, INT]),
     "gep_solve_batched": (INT, [INT, P, P, P, P, P, P, P, P, INT, INT, P, SZ, P, P]),
+    "gep_batched_threads": (INT, [INT]),
     "gep_reduce_workspace_size": (SZ, [I64]),
     "gep_reduce": (INT, [I64, P, I64, P, I64, P, I64, P, I64, P, SZ, P, P]),
     "gep_band_reduce_workspace_size": (SZ, [I64, INT]),

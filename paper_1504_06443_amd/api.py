@@ -140,6 +140,25 @@ def solve_explicit_inverse(A: torch.Tensor, B: torch.Tensor, check_info=True):
     return lam, Ycm.t()
 
 
+def solve_jacobi(A: torch.Tensor, B: torch.Tensor, check_info=True):
+    """All eigenpairs of A y = lambda B y through the reducer and the parallel block
+    Jacobi SEP solver (gep_solve_jacobi).  Returns (lam, Y) with Y^T B Y = I."""
+    A = _square(A, "A")
+    B = _square(B, "B")
+    M = A.shape[0]
+    dev = A.device
+    lam = torch.empty(M, dtype=torch.float64, device=dev)
+    Ycm = torch.empty((M, M), dtype=torch.float64, device=dev)  # column-major
+    ws = _workspace(lib().gep_workspace_size_jacobi(M), dev)
+    info = _info(dev)
+    st = lib().gep_solve_jacobi(M, _ptr(A), max(M, 1), _ptr(B), max(M, 1), _ptr(lam), _ptr(Ycm),
+                                max(M, 1), _ptr(ws), ws.numel(), _ptr(info), _stream())
+    check(st, "gep_solve_jacobi")
+    if check_info:
+        _raise_info(info, M, "gep_solve_jacobi")
+    return lam, Ycm.t()
+
+
 def reduce(A: torch.Tensor, B: torch.Tensor, check_info=True):
     """Reducer: (L, C) with B = L L^T and C = L^{-1} A L^{-T}."""
     A = _square(A, "A")

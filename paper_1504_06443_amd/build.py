@@ -13,11 +13,12 @@ LIB = os.path.join(HERE, "libgep.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["abi.hip", "gemm.hip", "misc.hip", "chol.hip", "band.hip", "bulge.hip", "dc.hip", "adjoint.hip",
-           "runtime.hip", "refine.hip", "tune.hip"]
+           "runtime.hip", "refine.hip", "tune.hip",
+           "jacobi.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          # packed-FP32 instructions stay off: they have produced silent wrong results
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-Wno-unused-result"]
+         "-Wall", "-Wextra", "-Werror", "-Wno-unused-result"]
 
 
 def _compile(src: str) -> str:

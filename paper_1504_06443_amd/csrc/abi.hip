@@ -5,6 +5,7 @@
 #include <cstring>
 #include <exception>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "../../include/gep.h"
@@ -544,6 +545,63 @@ void solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const doubl
     for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
 }
 
+// Block Jacobi SEP solver behind the reducer (the combination the paper's outlook
+// proposes, section 6): B = L L^T and C = L^{-1} A L^{-T} as in gep_solve, then
+// the eigenpairs of C by parallel block Jacobi, then Y = L^{-T} Z.  Phase events:
+// 0 start, 1 after the Cholesky factorization, 2 after C, 3 after the Jacobi
+// sweeps, 4 .. 10 after Y.
+int g_last_jacobi_sweeps = 0;
+
+struct JacobiPlan {
+  double *L, *Linv, *tmp, *C;
+  char* ws;
+  size_t ws_bytes;
+};
+
+void carve_jacobi(JacobiPlan& p, Arena& a, int64_t M) {
+  p.L = a.take<double>((size_t)M * M);
+  p.Linv = a.take<double>((size_t)cdiv(M, NB) * NB * NB);
+  p.tmp = a.take<double>((size_t)NB * M);
+  p.C = a.take<double>((size_t)M * M);
+  p.ws_bytes = jacobi_workspace(M);
+  p.ws = a.take<char>(p.ws_bytes);
+}
+
+void solve_jacobi(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                  double* lambda, double* Y, int64_t ldy, void* workspace, size_t ws_bytes,
+                  int32_t* info, hipStream_t s, bool prof_on) {
+  fill_i32(info, 1, 0, s);
+  if (M == 0) return;
+  JacobiPlan jp;
+  Arena a;
+  a.base = (char*)workspace;
+  a.cap = ws_bytes;
+  carve_jacobi(jp, a, M);
+  Prof prof(s);
+  Prof* pp = prof_on ? &prof : nullptr;
+  MathScope fp64(MathMode::Fp64);
+  if (pp) pp->mark(0);
+  copy_matrix(M, M, B, ldb, jp.L, M, s);
+  potrf_rec(jp.L, M, M, 0, jp.Linv, info, M, jp.tmp, s);
+  if (pp) pp->mark(1);
+  symmetrize_from_lower(M, A, lda, jp.C, M, s);
+  Tri t{jp.L, M, jp.Linv, 0};
+  trsm_lln(t, M, jp.C, M, M, jp.tmp, s);
+  trsm_rlt_lower(t, M, jp.C, M, jp.tmp, s);
+  symmetrize_from_lower(M, jp.C, M, jp.C, M, s);
+  if (pp) pp->mark(2);
+  Arena ja;
+  ja.base = jp.ws;
+  ja.cap = jp.ws_bytes;
+  g_last_jacobi_sweeps = jacobi_eig(M, jp.C, M, lambda, Y, ldy, info, ja, s);
+  if (pp) pp->mark(3);
+  trsm_llt(t, M, Y, ldy, M, jp.tmp, s);
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)M), dim3(256), 0, s, M, Y, ldy);
+  GEP_LAUNCH_CHECK();
+  if (pp)
+    for (int i = 4; i <= NPHASE; ++i) pp->mark(i);
+}
+
 // ---------------------------------------------------------------- batches
 // Instances run on NSTREAM worker streams forked from the caller's stream with
 // events (so the whole batch can be captured in one graph).  Longest-processing-
@@ -605,6 +663,9 @@ BatchPlan plan_batch(int batch, const int64_t* Mh, bool vectors) {
   bp.total = off + 256;
   return bp;
 }
+
+bool g_batched_threads = true;
+bool batched_threads() { return g_batched_threads; }
 
 struct Workers {
   hipStream_t st[NSTREAM];
@@ -847,6 +908,40 @@ int gep_solve_explicit_inverse(int64_t M, const double* A, int64_t lda, const do
   });
 }
 
+size_t gep_workspace_size_jacobi(int64_t M) {
+  if (M <= 0) return 256;
+  JacobiPlan jp;
+  Arena a;
+  a.dry = true;
+  carve_jacobi(jp, a, M);
+  return a.used + 256;
+}
+
+int gep_solve_jacobi(int64_t M, const double* A, int64_t lda, const double* B, int64_t ldb,
+                     double* lambda, double* Y, int64_t ldy, void* workspace, size_t ws_bytes,
+                     int32_t* info, void* stream) {
+  g_bad_arg = 0;
+  if (M < 0) return bad(1);
+  const int64_t m1 = M > 1 ? M : 1;
+  if (M > 0 && !A) return bad(2);
+  if (lda < m1) return bad(3);
+  if (M > 0 && !B) return bad(4);
+  if (ldb < m1) return bad(5);
+  if (M > 0 && !lambda) return bad(6);
+  if (M > 0 && !Y) return bad(7);
+  if (ldy < m1) return bad(8);
+  if (!info) return bad(11);
+  if (M > 0 && (!workspace || ((uintptr_t)workspace & 255))) return bad(9);
+  if (ws_bytes < gep_workspace_size_jacobi(M)) return GEP_ERR_WORKSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  return guarded([&]() -> int {
+    solve_jacobi(M, A, lda, B, ldb, lambda, Y, ldy, workspace, ws_bytes, info, s, true);
+    return GEP_OK;
+  });
+}
+
+int gep_last_jacobi_sweeps(void) { return g_last_jacobi_sweeps; }
+
 size_t gep_workspace_size_batched(int batch, const int64_t* M_host, int job, int prec) {
   (void)prec;
   if (batch <= 0 || !M_host) return 256;
@@ -889,12 +984,45 @@ int gep_solve_batched(int batch, const int64_t* M_host, const double* const* A_h
     Workers& w = workers();
     GEP_HIP(hipEventRecord(w.fork, s));
     for (int k = 0; k < NSTREAM; ++k) GEP_HIP(hipStreamWaitEvent(w.st[k], w.fork, 0));
-    for (int i : bp.order) {
-      const int k = bp.lane[i];
-      solve_one(M_host[i], A_host[i], lda_host[i], B_host[i], ldb_host[i], lambda_host[i],
-                vectors ? Y_host[i] : nullptr, vectors ? ldy_host[i] : 1, vectors,
-                (char*)workspace + bp.slot_off[k], bp.slot_bytes[k], info + i, w.st[k], false,
-                false);
+    auto lane_work = [&](int k) {
+      for (int i : bp.order) {
+        if (bp.lane[i] != k) continue;
+        solve_one(M_host[i], A_host[i], lda_host[i], B_host[i], ldb_host[i], lambda_host[i],
+                  vectors ? Y_host[i] : nullptr, vectors ? ldy_host[i] : 1, vectors,
+                  (char*)workspace + bp.slot_off[k], bp.slot_bytes[k], info + i, w.st[k], false,
+                  false);
+      }
+    };
+    // Each instance is a few hundred small launches, so one host thread cannot
+    // keep 16 streams fed: outside graph capture every stream's instances are
+    // enqueued by a thread of its own (the launches and their order on each
+    // stream are the same as from one thread, so the results are too).  Under
+    // capture one thread enqueues everything.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    GEP_HIP(hipStreamIsCapturing(s, &cs));
+    int lanes = 0;
+    for (int k = 0; k < NSTREAM; ++k)
+      if (bp.slot_bytes[k] > 0) ++lanes;
+    if (cs == hipStreamCaptureStatusNone && lanes > 1 && batched_threads()) {
+      int dev = 0;
+      GEP_HIP(hipGetDevice(&dev));
+      std::vector<int> rc(NSTREAM, GEP_OK);
+      std::vector<std::thread> th;
+      for (int k = 0; k < NSTREAM; ++k) {
+        if (bp.slot_bytes[k] == 0) continue;
+        th.emplace_back([&, k]() {
+          rc[k] = guarded([&]() -> int {
+            GEP_HIP(hipSetDevice(dev));
+            lane_work(k);
+            return GEP_OK;
+          });
+        });
+      }
+      for (auto& t : th) t.join();
+      for (int k = 0; k < NSTREAM; ++k)
+        if (rc[k] != GEP_OK) return rc[k];
+    } else {
+      for (int k = 0; k < NSTREAM; ++k) lane_work(k);
     }
     for (int k = 0; k < NSTREAM; ++k) {
       GEP_HIP(hipEventRecord(w.join[k], w.st[k]));
@@ -1167,6 +1295,11 @@ int gep_dgemm(int transA, int transB, int uplo, int64_t m, int64_t n, int64_t k,
 
 int gep_debug_force_wait_timeout(int on) {
   set_force_wait_timeout(on != 0);
+  return GEP_OK;
+}
+
+int gep_batched_threads(int on) {
+  g_batched_threads = on != 0;
   return GEP_OK;
 }
 

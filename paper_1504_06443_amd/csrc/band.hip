@@ -341,8 +341,8 @@ size_t panel_lds() { return sizeof(double) * 256 * (MAXB + 1); }
 
 // Largest grid of panel_qr_coop whose workgroups are all resident at once.
 int coop_blocks() {
-  static int cached = 0;
-  if (cached == 0) {
+  // computed once per process (thread-safe initialisation; retried if it throws)
+  static const int cached = [] {
     int dev = 0, cus = 0, per = 0;
     GEP_HIP(hipGetDevice(&dev));
     GEP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -350,9 +350,9 @@ int coop_blocks() {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)panel_lds()));
     GEP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)panel_qr_coop, NT,
                                                          panel_lds()));
-    cached = cus * (per > 0 ? per : 1);
-    if (cached > 512) cached = 512;
-  }
+    const int c = cus * (per > 0 ? per : 1);
+    return c > 512 ? 512 : c;
+  }();
   return cached;
 }
 

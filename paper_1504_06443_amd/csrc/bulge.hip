@@ -1063,6 +1063,172 @@ __device__ __forceinline__ void q2_apply_reg_body(const Q2Args& a) {
   }
 }
 
+// ---------------------------------------------------------------- FP32 arithmetic
+//
+// The same register-window application in FP32 arithmetic (the mixed-precision
+// path: Z, V and T rounded to FP32, products accumulated in FP32 on the matrix
+// cores, Z stored back in FP64).  v_mfma_f32_16x16x4f32 takes its operands in the
+// FP64 instruction's layout, but element r of lane l of its accumulator is row
+// 4 (l >> 4) + r of the 16 x 16 tile (FP64: (l >> 4) + 4 r).  Since the window
+// tiles are also the B operand of W = V^T Z, a k step of a tile now covers rows
+// {4 l4 + r} instead of {l4 + 4 r}; only the row and column indices of the V, T
+// and Z accesses change, the zero structure (tiles 0..4 / 1..5, T upper
+// triangular) is the same.
+struct ZColF {
+  double* z;      // this lane's column of Z (row 0 of the matrix)
+  bool ok;        // column inside Z
+  int64_t base;   // matrix row of window row 0
+  int64_t nrel;   // window rows inside the matrix
+};
+
+__device__ inline v4f zf_load(const ZColF& zc, int64_t tile) {
+  const int l4 = (threadIdx.x & 63) >> 4;
+  v4f v;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = 16 * tile + 4 * l4 + r;
+    v[r] = (zc.ok && row < zc.nrel) ? (float)zc.z[zc.base + row] : 0.0f;
+  }
+  return v;
+}
+
+__device__ inline void zf_store(const ZColF& zc, int64_t tile, const v4f& v) {
+  const int l4 = (threadIdx.x & 63) >> 4;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t row = 16 * tile + 4 * l4 + r;
+    if (zc.ok && row < zc.nrel) zc.z[zc.base + row] = (double)v[r];
+  }
+}
+
+__device__ inline void vt_commit_f32(const VTStage& f, float* Vs, float* Tt) {
+#pragma unroll
+  for (int i = 0; i < PV; ++i) {
+    const int idx = threadIdx.x + NT * i;
+    Vs[(idx >> 5) * VLD + (idx & 31)] = (float)f.v[i];
+  }
+#pragma unroll
+  for (int i = 0; i < PT; ++i) {
+    const int idx = threadIdx.x + NT * i;
+    Tt[(idx >> 5) * VLD + (idx & 31)] = (float)f.t[i];
+  }
+}
+
+__device__ inline v4f mfma_f32(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <int S0>
+__device__ __forceinline__ void q2_block_f32(const Q2Args& a, const Q2Pass& p, bool upper,
+                                             int64_t t, v4f (&Z)[8], float (*Vs)[HP * VLD],
+                                             float (*Tt)[NBW * VLD], int& cur) {
+  const int lane = threadIdx.x & 63, l15 = lane & 15, l4 = lane >> 4;
+  int64_t gn = 0, tn = 0;
+  const bool more = q2_next(a, p, upper, t, gn, tn);
+  VTStage st;
+  if (more) vt_fetch(a, gn, tn, st);
+  const float* V = Vs[cur];
+  const float* Tb = Tt[cur];
+  // W (32 x 16) = V^T Z; k step r of window tile u: rows 16 u + 4 l4 + r
+  v4f W0 = {0.0f, 0.0f, 0.0f, 0.0f}, W1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float* vr = V + (16 * u + 4 * l4 + r) * VLD + l15;
+      if (u <= 4) W0 = mfma_f32(vr[0], Z[(S0 + u) & 7][r], W0);
+      if (u >= 1) W1 = mfma_f32(vr[16], Z[(S0 + u) & 7][r], W1);
+    }
+  }
+  W0 = -W0;
+  W1 = -W1;
+  // X = T (-W); k step r: c = 4 l4 + r
+  v4f X0 = {0.0f, 0.0f, 0.0f, 0.0f}, X1 = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float* t0 = Tb + (4 * l4 + r) * VLD + l15;
+    const float* t1 = Tb + (16 + 4 * l4 + r) * VLD + l15;
+    X0 = mfma_f32(t0[0], W0[r], X0);
+    X1 = mfma_f32(t1[16], W1[r], X1);
+    X0 = mfma_f32(t1[0], W1[r], X0);
+  }
+  // Z += V X; k step r: c = 4 l4 + r
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int u = 0; u <= 4; ++u)
+      Z[(S0 + u) & 7] = mfma_f32(V[(16 * u + l15) * VLD + 4 * l4 + r], X0[r], Z[(S0 + u) & 7]);
+#pragma unroll
+    for (int u = 1; u < 6; ++u)
+      Z[(S0 + u) & 7] =
+          mfma_f32(V[(16 * u + l15) * VLD + 16 + 4 * l4 + r], X1[r], Z[(S0 + u) & 7]);
+  }
+  if (more) vt_commit_f32(st, Vs[cur ^ 1], Tt[cur ^ 1]);
+  __syncthreads();
+  cur ^= 1;
+}
+
+template <int P>
+__device__ __forceinline__ void q2_position_f32(const Q2Args& a, const Q2Pass& p,
+                                                const ZColF& zc, int64_t t, v4f (&Z)[8],
+                                                v4f (&S)[4], float (*Vs)[HP * VLD],
+                                                float (*Tt)[NBW * VLD], int& cur) {
+  constexpr int SL = (4 * P) & 7, SU = (4 * P + 2) & 7, SN = (4 * P + 4) & 7;
+  if (t >= 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Z[(SN + i) & 7] = S[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S[i] = zf_load(zc, 4 * t + 8 + i);
+  }
+  if (p.two && t < p.Ph) q2_block_f32<SU>(a, p, true, t, Z, Vs, Tt, cur);
+  q2_block_f32<SL>(a, p, false, t, Z, Vs, Tt, cur);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) zf_store(zc, 4 * t + i, Z[(SL + i) & 7]);
+}
+
+// 16 columns per wave, FP32 window (half the registers and LDS of the FP64 one).
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+q2_apply_reg_f32(Q2Args a) {
+  __shared__ float Vs[2][HP * VLD];
+  __shared__ float Tt[2][NBW * VLD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  ZColF zc;
+  const int64_t col = (int64_t)blockIdx.x * RCOLS + wave * 16 + (lane & 15);
+  zc.ok = col < a.ncols;
+  zc.z = a.Z + (zc.ok ? col : 0) * a.ldz;
+  if (a.ngroups <= 0) return;
+  int cur = 0;
+  {
+    const Q2Pass p = q2_pass(a, a.ngroups - 1);
+    VTStage st;
+    vt_fetch(a, p.Ph > 0 ? p.jh : p.jl, 0, st);
+    vt_commit_f32(st, Vs[0], Tt[0]);
+  }
+  __syncthreads();
+  v4f Z[8], S[4];
+  for (int64_t jh = a.ngroups - 1; jh >= 0; jh -= 2) {
+    const Q2Pass p = q2_pass(a, jh);
+    zc.base = p.base;
+    zc.nrel = p.nrel;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) Z[s] = zf_load(zc, s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S[i] = zf_load(zc, 8 + i);
+    for (int64_t t = 0; t < p.Pl; t += 2) {
+      q2_position_f32<0>(a, p, zc, t, Z, S, Vs, Tt, cur);
+      if (t + 1 < p.Pl) q2_position_f32<1>(a, p, zc, t + 1, Z, S, Vs, Tt, cur);
+    }
+    if ((p.Pl & 1) == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zf_store(zc, 4 * p.Pl + i, Z[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zf_store(zc, 4 * p.Pl + i, Z[4 + i]);
+    }
+  }
+}
+
 // One column group per wave, two waves per SIMD (two workgroups per CU): for
 // column counts that would leave CUs idle with 128 columns per workgroup.
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
@@ -1104,7 +1270,9 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
     // 32-bit byte offsets
     if (c.b == 64 && (32 * ldz + n) * 8 >= (int64_t)OOB)
       throw HipError{hipErrorInvalidValue, "leading dimension of Z too large"};
-    if (c.b == 64 && ncols >= tune("q2_wide_min_cols", n))
+    if (c.b == 64 && math_mode() == MathMode::Fp32 && tune("q2_mixed_fp32", n) == 1)
+      hipLaunchKernelGGL(q2_apply_reg_f32, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
+    else if (c.b == 64 && ncols >= tune("q2_wide_min_cols", n))
       hipLaunchKernelGGL(q2_apply_reg2, dim3((unsigned)cdiv(ncols, 2 * RCOLS)), dim3(NT), 0, s, a);
     else if (c.b == 64)
       hipLaunchKernelGGL(q2_apply_reg, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);

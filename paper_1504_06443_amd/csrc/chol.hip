@@ -120,12 +120,13 @@ size_t potrf_leaf_lds() { return sizeof(double) * ((size_t)NB * LDS_LD + NB); }
 
 void potrf_leaf(int64_t n, double* a, int64_t lda, double* linv_blk, int32_t* info, int64_t row0,
                 int64_t info_add, hipStream_t s) {
-  static bool attr_set = false;
-  if (!attr_set) {
+  // set once per process (thread-safe initialisation; retried if it throws)
+  static const bool attr_set = [] {
     GEP_HIP(hipFuncSetAttribute((const void*)potrf_trtri_leaf,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)potrf_leaf_lds()));
-    attr_set = true;
-  }
+    return true;
+  }();
+  (void)attr_set;
   hipLaunchKernelGGL(potrf_trtri_leaf, dim3(1), dim3(NT), potrf_leaf_lds(), s, (int)n, a, lda,
                      linv_blk, info, row0, info_add);
   GEP_LAUNCH_CHECK();

@@ -118,6 +118,7 @@ struct ProbeScope {
   hipStream_t s;
   double flops;
   bool on;
+  hipEvent_t start, stop;  // this launch's pair (the record is kept when the scope ends)
   ProbeScope(int id_, hipStream_t s_, double flops_);
   ~ProbeScope();
   ProbeScope(const ProbeScope&) = delete;
@@ -137,6 +138,8 @@ void fill_f64(double* p, int64_t n, double v, hipStream_t s);
 // Enqueue: if *flag != 0, set *info = code unless info already holds a failure.
 // A one-thread kernel, so it needs no host synchronisation and can be captured.
 void raise_info_if(const int32_t* flag, int32_t* info, int32_t code, hipStream_t s);
+// Enqueue: *info = code unless info already holds a failure.
+void raise_info(int32_t* info, int32_t code, hipStream_t s);
 
 // Device-side failure codes written to info besides the LAPACK ones (mirrored in
 // gep.h): a bounded wait between workgroups gave up, or the mixed-precision

@@ -86,6 +86,16 @@ void stedc(int64_t n, const double* d, const double* e, double* lambda, double* 
 void stebz_ws(int64_t n, const double* d, const double* e, double* lambda, double* bounds2,
               hipStream_t s);
 
+// ---------------------------------------------------------------- block Jacobi SEP
+// Eigenvalues (ascending, into lam) and eigenvectors (into Z, ldz) of the
+// symmetric n x n matrix C (full storage, destroyed) by parallel two-sided block
+// Jacobi.  Synchronises the stream once per sweep (convergence test on the
+// host).  info <- n if it has not converged after 30 sweeps.  Returns the number
+// of sweeps.
+size_t jacobi_workspace(int64_t n);
+int jacobi_eig(int64_t n, double* C, int64_t ldc, double* lam, double* Z, int64_t ldz,
+               int32_t* info, Arena& ws, hipStream_t s);
+
 // ---------------------------------------------------------------- adjoint
 size_t backward_workspace(int64_t M);
 void backward(int64_t M, const double* lam, const double* Y, int64_t ldy, const double* lam_bar,

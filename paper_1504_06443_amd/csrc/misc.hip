@@ -67,6 +67,7 @@ __global__ void fill_f64_kernel(double* p, int64_t n, double v) {
 __global__ void flag_to_info_kernel(const int32_t* flag, int32_t* info, int32_t code) {
   if (*flag != 0) atomicCAS(info, 0, code);
 }
+__global__ void info_if_zero_kernel(int32_t* info, int32_t code) { atomicCAS(info, 0, code); }
 
 dim3 grid2(int64_t m, int64_t n) {
   return dim3((unsigned)cdiv(m, TX), (unsigned)cdiv(cdiv(n, COLS_PER), TY));
@@ -110,6 +111,12 @@ void fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 void fill_f64(double* p, int64_t n, double v, hipStream_t s) {
   if (n <= 0) return;
   hipLaunchKernelGGL(fill_f64_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, p, n, v);
+  GEP_LAUNCH_CHECK();
+}
+
+void raise_info(int32_t* info, int32_t code, hipStream_t s) {
+  if (!info) return;
+  hipLaunchKernelGGL(info_if_zero_kernel, dim3(1), dim3(1), 0, s, info, code);
   GEP_LAUNCH_CHECK();
 }
 

@@ -103,7 +103,8 @@ __global__ void __launch_bounds__(NT) partition_blocks(int64_t M, const double* 
 // T = L L^T, C = L^-1 S L^-T, cyclic Jacobi (round-robin pairs, all disjoint
 // rotations of a round applied together), W = L^-T Z, eigenpairs sorted
 // ascending.  Writes W into K (rows s0.., columns 0..n-1, leading dimension ldk).
-__global__ void __launch_bounds__(NT) block_eig(int64_t M, const double* __restrict__ S,
+__global__ void __launch_bounds__(NT) block_eig([[maybe_unused]] int64_t M,
+                                                const double* __restrict__ S,
                                                 const double* __restrict__ T, int64_t ld,
                                                 const int32_t* __restrict__ starts,
                                                 const int32_t* __restrict__ nblk,

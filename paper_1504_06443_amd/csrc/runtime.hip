@@ -58,25 +58,24 @@ void probe_enable(bool on) {
   g_probe_on = on;
 }
 
-ProbeScope::ProbeScope(int id_, hipStream_t s_, double flops_) : id(id_), s(s_), flops(flops_) {
+ProbeScope::ProbeScope(int id_, hipStream_t s_, double flops_)
+    : id(id_), s(s_), flops(flops_), start(nullptr), stop(nullptr) {
   std::lock_guard<std::mutex> lk(g_probe_mu);
   on = g_probe_on && id >= 0 && id < PROBE_COUNT;
   if (!on) return;
-  ProbeRecord r;
-  r.start = take_event();
-  r.stop = take_event();
-  r.flops = flops;
-  GEP_HIP(hipEventRecord(r.start, s));
-  g_records[id].push_back(r);
+  start = take_event();
+  stop = take_event();
+  GEP_HIP(hipEventRecord(start, s));
 }
 
 ProbeScope::~ProbeScope() {
   if (!on) return;
+  // The scope owns its event pair, so launches from several host threads stay
+  // paired.  A destructor does not throw: a failed record shows up when the
+  // events are read.
+  (void)hipEventRecord(stop, s);
   std::lock_guard<std::mutex> lk(g_probe_mu);
-  // the record pushed by this scope is the last one of its kind: launches of one
-  // kind are issued one at a time from the host.  A destructor does not throw: a
-  // failed record shows up when the events are read.
-  (void)hipEventRecord(g_records[id].back().stop, s);
+  g_records[id].push_back(ProbeRecord{start, stop, flops});
 }
 
 bool probe_read(int id, int64_t* launches, double* ms, double* flops) {

@@ -42,6 +42,7 @@ const Param kParams[] = {
     {"dc_leaf", 8, 64},               // divide-and-conquer leaf order
     {"symm_split_rows", 1, INT64_MAX},   // the band reduction's symmetric product splits K from here
     {"chase_extra_groups", 0, 512},   // bulge chase workgroups beyond half the positions
+    {"q2_mixed_fp32", 0, 1},          // mixed precision: Q2 in FP32 arithmetic (1) or FP64
 };
 
 bool known(const std::string& k, const Param** out) {
@@ -258,6 +259,9 @@ int64_t default_value(const std::string& k, int64_t M) {
   if (k == "dc_leaf") return 64;
   if (k == "symm_split_rows") return 2048;
   if (k == "chase_extra_groups") return 8;
+  // FP32 Q2 measured slower than FP64 Q2 at M = 32768 (2485 against 2330 ms): the
+  // phase is bound by its per-block latencies, not by the matrix cores
+  if (k == "q2_mixed_fp32") return 0;
   return -1;
 }
 

@@ -263,3 +263,18 @@ def test_tuning_table_api(lib, tmp_path):
     lib.gep_tune_clear()
     assert get("band_width", 100) == 16
     lib.gep_tune_load(None)  # back to the default location (the committed table, if any)
+
+
+def test_jacobi_entry_rejects_bad_arguments(lib):
+    P = ctypes.c_void_p
+    f = P(0x100000)
+    w = P(0x200000)
+    need = lib.gep_workspace_size_jacobi(50)
+    assert need > lib.gep_workspace_size_jacobi(10) > 0
+    assert lib.gep_solve_jacobi(-1, f, 1, f, 1, f, f, 1, w, need, f, None) == -1
+    assert lib.gep_last_bad_arg() == 1
+    assert lib.gep_solve_jacobi(50, f, 49, f, 50, f, f, 50, w, need, f, None) == -1
+    assert lib.gep_last_bad_arg() == 3
+    assert lib.gep_solve_jacobi(50, f, 50, f, 50, f, f, 50, w, need, None, None) == -1
+    assert lib.gep_last_bad_arg() == 11
+    assert lib.gep_solve_jacobi(50, f, 50, f, 50, f, f, 50, w, need - 1, f, None) == -2
