@@ -369,7 +369,13 @@ const char* gep_probe_name(int kernel);
  *                       positions (0..512; 8);
  *   q2_mixed_fp32       GEP_PREC_MIXED: the Q2 back transformation in FP32
  *                       arithmetic on the matrix cores (1) or in FP64 (0; built
- *                       in: 0, measured faster at M = 32768).
+ *                       in: 0, measured faster at M = 32768);
+ *   q2_staged           FP64 Q2 back transformation with 16 columns per wave:
+ *                       V / T staged by direct-to-LDS loads and Z read and
+ *                       written in 16-byte accesses (1; needs an even leading
+ *                       dimension and a 16-byte aligned Z, else the
+ *                       register-staged kernel runs) or the register-staged
+ *                       kernel (0).  Built in: 1.
  * Results depend on band_width and dc_leaf only through rounding; every
  * parameter value gives a correct solve.  A batched instance and a single solve
  * of the same order use the same values.

@@ -439,7 +439,18 @@ struct Q2Args {
   double* T;  // NBW x NBW per block (group j, position k) at T + (j*kmax + k)*NBW*NBW
   double* Z;
   int64_t ldz, ncols;
+  int swizzle;  // q2_form_t rewrites V and T in the swizzled staging layout
 };
+
+// The 16-byte pair permutation of row R of a staged 32-column LDS array: pair p
+// of the row is stored at p ^ swz_key(R).  The key is a bijection of R mod 16 that
+// also flips bit 3 when bit 0 xor bit 2 of R is set, so that the two rows read
+// together by 32 lanes (R and R + 4 in W = V^T Z, R and R + 1 in the T reads)
+// land in opposite halves of the row's 16 pairs, and the 16 rows read by one
+// column in Z += V X take 16 distinct pairs.
+__host__ __device__ inline int swz_key(int row) {
+  return (row & 15) ^ ((((row >> 2) ^ row) & 1) << 3);
+}
 
 // T factor of every block (forward accumulation, H_{s0} ... H_{s0+NBW-1} =
 // I - V T V^T), stored transposed (T^T row-major == T column-major).
@@ -453,7 +464,7 @@ __global__ void __launch_bounds__(NT) q2_form_t(Q2Args a) {
   if (k >= positions(a.n, a.b, s0)) return;
   const double* blk = a.V + (j * a.kmax + k) * (int64_t)(HP * NBW);
   const int H = a.b + NBW - 1;
-  for (int idx = threadIdx.x; idx < H * NBW; idx += NT)
+  for (int idx = threadIdx.x; idx < (a.swizzle ? HP : H) * NBW; idx += NT)
     Vs[(idx / NBW) * (NBW + 1) + idx % NBW] = blk[idx];
   for (int c = threadIdx.x; c < NBW; c += NT) {
     const int64_t s = s0 + c;
@@ -481,7 +492,25 @@ __global__ void __launch_bounds__(NT) q2_form_t(Q2Args a) {
     __syncthreads();
   }
   double* out = a.T + (j * a.kmax + k) * NBW * NBW;
-  for (int idx = threadIdx.x; idx < NBW * NBW; idx += NT) out[idx] = Ts[idx % NBW][idx / NBW];
+  if (!a.swizzle) {
+    for (int idx = threadIdx.x; idx < NBW * NBW; idx += NT) out[idx] = Ts[idx % NBW][idx / NBW];
+    return;
+  }
+  // staging layout: row-major rows of 32, 16-byte pairs of a row permuted by
+  // pair ^ swz_key(row); element (row, col) of T^T and of V at swz(row, col)
+  for (int idx = threadIdx.x; idx < NBW * NBW; idx += NT) {
+    const int row = idx >> 5, pc = idx & 31;
+    const int col = (((pc >> 1) ^ swz_key(row)) << 1) | (pc & 1);
+    out[idx] = Ts[col][row];
+  }
+  // V's row i lands in LDS row i + 1 (row 0 there is zero: the window starts one
+  // row above the block's first row)
+  double* blkw = const_cast<double*>(a.V) + (j * a.kmax + k) * (int64_t)(HP * NBW);
+  for (int idx = threadIdx.x; idx < HP * NBW; idx += NT) {
+    const int row = idx >> 5, pc = idx & 31;
+    const int col = (((pc >> 1) ^ swz_key(row + 1)) << 1) | (pc & 1);
+    blkw[idx] = Vs[row * (NBW + 1) + col];
+  }
 }
 
 // Z <- (I - V T V^T) Z for every block, groups from last to first, positions in
@@ -996,6 +1025,239 @@ __device__ __forceinline__ void q2_position(const Q2Args& a, const Q2Pass& p, co
     for (int i = 0; i < 4; ++i) z_store(zc, g, 4 * t + i, Z[g][(SL + i) & 7]);
 }
 
+// ---------------------------------------------------------------- b = 64: staged window
+//
+// The same register window with its memory traffic reshaped.  Timing copies of
+// the register-staged kernel that skipped one memory stream each ran 15-19%
+// faster per stream (Z stores, Z prefetch loads, V / T staging): the phase is
+// bound by its vector-memory traffic, not by the matrix cores.  Here
+//  - V and T reach LDS through direct-to-LDS loads (1 KB per instruction, eight
+//    per wave per block): no registers hold them and no LDS stores are issued.
+//    q2_form_t writes both in the LDS layout (rows of 32, the 16-byte pairs of
+//    row R permuted by pair ^ swz_key(R), so that the row-wise reads of W = V^T Z
+//    and the column-wise reads of Z += V X stay spread over the banks);
+//  - inside each 16-row tile the rows are relabelled so that accumulator element
+//    r of lane (l15, l4) is tile row 4 l4 + r (V's rows are relabelled alike; the
+//    products are unchanged): a lane holds four consecutive rows of its column,
+//    read and written as two 16-byte accesses instead of four 8-byte ones;
+//  - the window starts one row above the pass's first row (at jl NBW, an even
+//    row), so those accesses are 16-byte aligned given an even leading dimension;
+//    that row meets a zero row of V (LDS row 0) and is written back unchanged.
+// Window rows past the matrix use the 8-byte accesses with out-of-range offsets.
+
+// Element (row, col) of a staged 32-column LDS array.
+__device__ __forceinline__ int swz(int row, int col) {
+  return row * 32 + ((((col >> 1) ^ swz_key(row)) << 1) | (col & 1));
+}
+
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+// Wait until this wave's direct-to-LDS loads have written LDS: first the loads
+// (vector memory count), then, in an instruction of its own, the LDS writes they
+// queued (LDS count).  One combined wait may find the LDS count at zero before
+// the last load has queued its write.
+__device__ __forceinline__ void dma_landed() {
+  asm volatile("s_waitcnt vmcnt(0)\n\ts_waitcnt lgkmcnt(0)" ::: "memory");
+}
+
+// Block (g, t)'s V (24 KB) and T (8 KB) into LDS in 1 KB direct-to-LDS loads,
+// eight per wave; no registers hold them and no LDS stores are issued.
+__device__ __forceinline__ void vt_dma(const Q2Args& a, int64_t g, int64_t t, double* Vd,
+                                       double* Td) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const char* vsrc = (const char*)(a.V + (g * a.kmax + t) * (int64_t)(HP * NBW));
+  const char* tsrc = (const char*)(a.T + (g * a.kmax + t) * NBW * NBW);
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int q = wave * 8 + i;
+    if (q < 24)
+      __builtin_amdgcn_global_load_lds((const void*)(vsrc + q * 1024 + lane * 16),
+                                       (lds_ptr)((char*)Vd + q * 1024), 16, 0, 0);
+    else
+      __builtin_amdgcn_global_load_lds((const void*)(tsrc + (q - 24) * 1024 + lane * 16),
+                                       (lds_ptr)((char*)Td + (q - 24) * 1024), 16, 0, 0);
+  }
+}
+
+// The wave's columns of Z for the staged kernel: window row w is matrix row
+// base + w, with base = jl NBW (one above the pass's first row, even).
+struct ZColS {
+  __amdgpu_buffer_rsrc_t rsrc;  // the wave's 16 columns
+  uint32_t coff;                // byte offset of the lane's column + 32 l4, or OOB
+  int64_t base;                 // matrix row of window row 0 (even)
+  int64_t nrel;                 // window rows inside the matrix
+};
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2v __attribute__((ext_vector_type(2)));
+
+__device__ inline v4d zs_load(const ZColS& zc, int64_t tile) {
+  v4d v;
+  const int l4 = (threadIdx.x & 63) >> 4;
+  const int64_t row0 = 16 * tile;
+  if (row0 + 16 <= zc.nrel) {
+    const uint32_t off = zc.coff == OOB ? OOB : zc.coff + (uint32_t)((zc.base + row0) * 8);
+    const u32x4 lo = __builtin_amdgcn_raw_buffer_load_b128(zc.rsrc, off, 0, 0);
+    const u32x4 hi = __builtin_amdgcn_raw_buffer_load_b128(zc.rsrc, off == OOB ? OOB : off + 16, 0, 0);
+    v[0] = __builtin_bit_cast(double, u32x2v{lo.x, lo.y});
+    v[1] = __builtin_bit_cast(double, u32x2v{lo.z, lo.w});
+    v[2] = __builtin_bit_cast(double, u32x2v{hi.x, hi.y});
+    v[3] = __builtin_bit_cast(double, u32x2v{hi.z, hi.w});
+  } else {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 4 * l4 + r;
+      const uint32_t off = (zc.coff != OOB && row < zc.nrel)
+                               ? zc.coff - 32 * l4 + (uint32_t)((zc.base + row) * 8)
+                               : OOB;
+      v[r] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(zc.rsrc, off, 0, 0));
+    }
+  }
+  return v;
+}
+
+__device__ inline void zs_store(const ZColS& zc, int64_t tile, const v4d& v) {
+  const int l4 = (threadIdx.x & 63) >> 4;
+  const int64_t row0 = 16 * tile;
+  const double x0 = v[0], x1 = v[1], x2 = v[2], x3 = v[3];
+  const u32x2v a0 = __builtin_bit_cast(u32x2v, x0), a1 = __builtin_bit_cast(u32x2v, x1),
+               a2 = __builtin_bit_cast(u32x2v, x2), a3 = __builtin_bit_cast(u32x2v, x3);
+  if (row0 + 16 <= zc.nrel) {
+    const uint32_t off = zc.coff == OOB ? OOB : zc.coff + (uint32_t)((zc.base + row0) * 8);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{a0.x, a0.y, a1.x, a1.y}, zc.rsrc, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(u32x4{a2.x, a2.y, a3.x, a3.y}, zc.rsrc,
+                                           off == OOB ? OOB : off + 16, 0, 0);
+  } else {
+    const u32x2v e[4] = {a0, a1, a2, a3};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + 4 * l4 + r;
+      const uint32_t off = (zc.coff != OOB && row < zc.nrel)
+                               ? zc.coff - 32 * l4 + (uint32_t)((zc.base + row) * 8)
+                               : OOB;
+      __builtin_amdgcn_raw_buffer_store_b64(e[r], zc.rsrc, off, 0, 0);
+    }
+  }
+}
+
+constexpr int VROWS = HP + 1;  // LDS rows of a V buffer (row 0 zero)
+
+template <int S0>
+__device__ __forceinline__ void q2_block_staged(const Q2Args& a, const Q2Pass& p, bool upper,
+                                            int64_t t, v4d (&Z)[8], double (*Vs)[VROWS * 32],
+                                            double (*Tt)[NBW * 32], int& cur) {
+  const int lane = threadIdx.x & 63, l15 = lane & 15, l4 = lane >> 4;
+  const int pl = 4 * (l15 & 3) + (l15 >> 2);  // tile row of lane l15 as an output row
+  int64_t gn = 0, tn = 0;
+  const bool more = q2_next(a, p, upper, t, gn, tn);
+  if (more) vt_dma(a, gn, tn, Vs[cur ^ 1] + 32, Tt[cur ^ 1]);
+  const double* V = Vs[cur];
+  const double* Tb = Tt[cur];
+  v4d W0 = {0.0, 0.0, 0.0, 0.0}, W1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int u = 0; u < 6; ++u) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * u + 4 * l4 + r;
+      if (u <= 4) W0 = __builtin_amdgcn_mfma_f64_16x16x4f64(V[swz(row, l15)], Z[(S0 + u) & 7][r], W0, 0, 0, 0);
+      if (u >= 1) W1 = __builtin_amdgcn_mfma_f64_16x16x4f64(V[swz(row, 16 + l15)], Z[(S0 + u) & 7][r], W1, 0, 0, 0);
+    }
+  }
+  W0 = -W0;
+  W1 = -W1;
+  v4d X0 = {0.0, 0.0, 0.0, 0.0}, X1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const double t00 = Tb[swz(4 * r + l4, l15)], t11 = Tb[swz(16 + 4 * r + l4, 16 + l15)],
+                 t10 = Tb[swz(16 + 4 * r + l4, l15)];
+    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t00, W0[r], X0, 0, 0, 0);
+    X1 = __builtin_amdgcn_mfma_f64_16x16x4f64(t11, W1[r], X1, 0, 0, 0);
+    X0 = __builtin_amdgcn_mfma_f64_16x16x4f64(t10, W1[r], X0, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+#pragma unroll
+    for (int u = 0; u <= 4; ++u)
+      Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(V[swz(16 * u + pl, 4 * r + l4)], X0[r], Z[(S0 + u) & 7], 0, 0, 0);
+#pragma unroll
+    for (int u = 1; u < 6; ++u)
+      Z[(S0 + u) & 7] = __builtin_amdgcn_mfma_f64_16x16x4f64(V[swz(16 * u + pl, 16 + 4 * r + l4)], X1[r], Z[(S0 + u) & 7], 0, 0, 0);
+  }
+  dma_landed();
+  __syncthreads();
+  cur ^= 1;
+}
+
+template <int P>
+__device__ __forceinline__ void q2_position_staged(const Q2Args& a, const Q2Pass& p, const ZColS& zc,
+                                               int64_t t, v4d (&Z)[8], v4d (&S)[4],
+                                               double (*Vs)[VROWS * 32], double (*Tt)[NBW * 32],
+                                               int& cur) {
+  constexpr int SL = (4 * P) & 7, SU = (4 * P + 2) & 7, SN = (4 * P + 4) & 7;
+  if (t >= 1) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Z[(SN + i) & 7] = S[i];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S[i] = zs_load(zc, 4 * t + 8 + i);
+  }
+  if (p.two && t < p.Ph) q2_block_staged<SU>(a, p, true, t, Z, Vs, Tt, cur);
+  q2_block_staged<SL>(a, p, false, t, Z, Vs, Tt, cur);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) zs_store(zc, 4 * t + i, Z[(SL + i) & 7]);
+}
+
+__device__ __forceinline__ void q2_apply_staged_body(const Q2Args& a) {
+  __shared__ double Vs[2][VROWS * 32];
+  __shared__ double Tt[2][NBW * 32];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  ZColS zc;
+  {
+    const int64_t wcol = (int64_t)blockIdx.x * RCOLS + wave * 16;
+    int64_t nw = a.ncols - wcol;
+    if (nw > 16) nw = 16;
+    if (nw < 0) nw = 0;
+    const int64_t bytes = nw > 0 ? ((nw - 1) * a.ldz + a.n) * 8 : 0;
+    zc.rsrc = __builtin_amdgcn_make_buffer_rsrc(a.Z + (nw > 0 ? wcol : 0) * a.ldz, (short)0,
+                                                (int)bytes, 0x00020000);
+    const int c = lane & 15;
+    zc.coff = c < nw ? (uint32_t)(c * a.ldz * 8 + 32 * (lane >> 4)) : OOB;
+  }
+  if (a.ngroups <= 0) return;
+  if (tid < 32) {
+    Vs[0][tid] = 0.0;
+    Vs[1][tid] = 0.0;
+  }
+  int cur = 0;
+  {
+    const Q2Pass p = q2_pass(a, a.ngroups - 1);
+    vt_dma(a, p.Ph > 0 ? p.jh : p.jl, 0, Vs[0] + 32, Tt[0]);
+    dma_landed();
+  }
+  __syncthreads();
+  v4d Z[8], S[4];
+  for (int64_t jh = a.ngroups - 1; jh >= 0; jh -= 2) {
+    const Q2Pass p = q2_pass(a, jh);
+    zc.base = p.base - 1;
+    zc.nrel = p.nrel + 1;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) Z[s] = zs_load(zc, s);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) S[i] = zs_load(zc, 8 + i);
+    for (int64_t t = 0; t < p.Pl; t += 2) {
+      q2_position_staged<0>(a, p, zc, t, Z, S, Vs, Tt, cur);
+      if (t + 1 < p.Pl) q2_position_staged<1>(a, p, zc, t + 1, Z, S, Vs, Tt, cur);
+    }
+    if ((p.Pl & 1) == 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zs_store(zc, 4 * p.Pl + i, Z[i]);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) zs_store(zc, 4 * p.Pl + i, Z[4 + i]);
+    }
+  }
+}
+
 // The whole Q2 application for the G column groups of each wave: 64 G columns
 // per workgroup of four waves.
 template <int G>
@@ -1236,6 +1498,13 @@ q2_apply_reg(Q2Args a) {
   q2_apply_reg_body<1>(a);
 }
 
+// The staged window (16 columns per wave, two waves per SIMD): the default for
+// FP64 with b = 64.
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+q2_apply_staged(Q2Args a) {
+  q2_apply_staged_body(a);
+}
+
 // Two column groups per wave, one wave per SIMD: the full register file (no
 // spills) and twice the independent MFMA chains per wave.
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(1, 1)))
@@ -1260,6 +1529,20 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
   Q2Args a;
   a.n = n; a.b = c.b; a.nsweeps = nsweeps; a.kmax = c.kmax; a.ngroups = cdiv(nsweeps, NBW);
   a.V = c.V; a.tau = c.tau; a.Z = Z; a.ldz = ldz; a.ncols = ncols;
+  enum class Kernel { Lds, Reg, Reg2, RegF32, Staged } kern = Kernel::Lds;
+  if (c.b == 64) {
+    if (math_mode() == MathMode::Fp32 && tune("q2_mixed_fp32", n) == 1)
+      kern = Kernel::RegF32;
+    else if (ncols >= tune("q2_wide_min_cols", n))
+      kern = Kernel::Reg2;
+    else if (tune("q2_staged", n) == 1 && ldz % 2 == 0 && ((uintptr_t)Z & 15) == 0)
+      kern = Kernel::Staged;
+    else
+      kern = Kernel::Reg;
+  }
+  // the staged kernel reads V and T in its swizzled layout, which q2_form_t then
+  // writes (V in place: the chase's reflectors are consumed by this one call)
+  a.swizzle = kern == Kernel::Staged ? 1 : 0;
   a.T = ws.take<double>((size_t)a.ngroups * a.kmax * NBW * NBW);
   hipLaunchKernelGGL(q2_form_t, dim3((unsigned)a.kmax, (unsigned)a.ngroups), dim3(NT), 0, s, a);
   GEP_LAUNCH_CHECK();
@@ -1270,14 +1553,23 @@ void apply_q2(const BulgeChase& c, double* Z, int64_t ldz, int64_t ncols, Arena&
     // 32-bit byte offsets
     if (c.b == 64 && (32 * ldz + n) * 8 >= (int64_t)OOB)
       throw HipError{hipErrorInvalidValue, "leading dimension of Z too large"};
-    if (c.b == 64 && math_mode() == MathMode::Fp32 && tune("q2_mixed_fp32", n) == 1)
-      hipLaunchKernelGGL(q2_apply_reg_f32, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
-    else if (c.b == 64 && ncols >= tune("q2_wide_min_cols", n))
-      hipLaunchKernelGGL(q2_apply_reg2, dim3((unsigned)cdiv(ncols, 2 * RCOLS)), dim3(NT), 0, s, a);
-    else if (c.b == 64)
-      hipLaunchKernelGGL(q2_apply_reg, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
-    else
-      hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
+    switch (kern) {
+      case Kernel::RegF32:
+        hipLaunchKernelGGL(q2_apply_reg_f32, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
+        break;
+      case Kernel::Reg2:
+        hipLaunchKernelGGL(q2_apply_reg2, dim3((unsigned)cdiv(ncols, 2 * RCOLS)), dim3(NT), 0, s, a);
+        break;
+      case Kernel::Staged:
+        hipLaunchKernelGGL(q2_apply_staged, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
+        break;
+      case Kernel::Reg:
+        hipLaunchKernelGGL(q2_apply_reg, dim3((unsigned)cdiv(ncols, RCOLS)), dim3(NT), 0, s, a);
+        break;
+      case Kernel::Lds:
+        hipLaunchKernelGGL(q2_apply, dim3((unsigned)cdiv(ncols, SWA)), dim3(NT), 0, s, a);
+        break;
+    }
     GEP_LAUNCH_CHECK();
   }
 }

@@ -43,6 +43,7 @@ const Param kParams[] = {
     {"symm_split_rows", 1, INT64_MAX},   // the band reduction's symmetric product splits K from here
     {"chase_extra_groups", 0, 512},   // bulge chase workgroups beyond half the positions
     {"q2_mixed_fp32", 0, 1},          // mixed precision: Q2 in FP32 arithmetic (1) or FP64
+    {"q2_staged", 0, 1},              // FP64 Q2: the DMA-staged 16-byte window kernel (1) or not
 };
 
 bool known(const std::string& k, const Param** out) {
@@ -262,6 +263,9 @@ int64_t default_value(const std::string& k, int64_t M) {
   // FP32 Q2 measured slower than FP64 Q2 at M = 32768 (2485 against 2330 ms): the
   // phase is bound by its per-block latencies, not by the matrix cores
   if (k == "q2_mixed_fp32") return 0;
+  // V / T staged by direct-to-LDS loads and Z moved in 16-byte accesses: S4 at
+  // M = 32768 1983 against 2355 ms with the register-staged kernel
+  if (k == "q2_staged") return 1;
   return -1;
 }
 

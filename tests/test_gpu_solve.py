@@ -340,6 +340,41 @@ def test_solve_band64_wide_q2(gpu, M):
     assert worst <= 1e-11 * n1, worst
 
 
+@pytest.mark.parametrize("M", [2080, 2113, 3000])
+def test_solve_band64_staged_vs_register_q2(gpu, M):
+    """The staged Q2 kernel (direct-to-LDS V / T, 16-byte Z accesses, window one
+    row above the pass) is the default for an even leading dimension; the
+    register-staged kernel runs for odd ones (M = 2113) and when q2_staged = 0.
+    Both checked against each other at ragged orders (partial last workgroup,
+    window rows past the matrix, odd numbers of sweep groups) and on the
+    invariants, and a partial solve (k = 1000 transformed columns, not a multiple
+    of the 64 per workgroup) against the full solve's vectors."""
+    say(f"[solve] band 64, staged vs register-staged Q2, M={M}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 900 + M)
+    lam0, Y0 = _gep().solve(to_gpu(A), to_gpu(B))
+    _tune("q2_staged", M, M, 0)
+    try:
+        lam1, Y1 = _gep().solve(to_gpu(A), to_gpu(B))
+    finally:
+        _tune_reset()
+    n1 = np.abs(A).sum(axis=0).max()
+    lam0, Y0, lam1, Y1 = to_np(lam0), to_np(Y0), to_np(lam1), to_np(Y1)
+    assert np.abs(lam1 - lam0).max() <= 1e-13 * n1
+    for Y, lam in ((Y0, lam0), (Y1, lam1)):
+        orth = np.abs(Y.T @ B @ Y - np.eye(M)).max()
+        assert orth <= TOL_ORTH, orth
+        res = np.abs(A @ Y - B @ Y * lam[None, :]).sum(axis=0).max() / (n1 * np.abs(Y).sum(axis=0).max())
+        assert res <= TOL_RES, res
+    worst = max_subspace_sine(Y1, Y0, B, lam0, 1e-8 * n1)
+    assert worst <= 1e-11 * n1, worst
+    k = 1000
+    lamk, Yk = _gep().solve_lowest(to_gpu(A), to_gpu(B), k)
+    lamk, Yk = to_np(lamk), to_np(Yk)
+    assert np.abs(lamk - lam0).max() <= 1e-13 * n1
+    worst = max_subspace_sine(Yk, Y0[:, :k], B, lam0[:k], 1e-8 * n1)
+    assert worst <= 1e-11 * n1, worst
+
+
 @pytest.mark.parametrize("key,value", [("band_width", 8), ("band_width", 24), ("band_width", 48),
                                        ("band_width", 64), ("dc_leaf", 16), ("dc_leaf", 40),
                                        ("chase_extra_groups", 0), ("symm_split_rows", 64)])
