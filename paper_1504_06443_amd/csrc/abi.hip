@@ -51,7 +51,13 @@ __global__ void sign_fix_kernel(int64_t n, double* __restrict__ Y, int64_t ldy) 
     }
     __syncthreads();
   }
-  if (y[bi[0]] < 0.0)
+  // One thread reads the pivot's sign before any entry of the column changes: a
+  // wave that read it after another wave had already negated it would skip the
+  // flip and leave the column half negated.
+  __shared__ int flip;
+  if (threadIdx.x == 0) flip = y[bi[0]] < 0.0;
+  __syncthreads();
+  if (flip)
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) y[i] = -y[i];
 }
 
