@@ -376,6 +376,11 @@ const char* gep_probe_name(int kernel);
  *                       dimension and a 16-byte aligned Z, else the
  *                       register-staged kernel runs) or the register-staged
  *                       kernel (0).  Built in: 1.
+ *   chase_stationary    single solves (not batched ones): the data-stationary
+ *                       bulge chase, each workgroup keeping its positions' blocks
+ *                       in LDS across sweeps (1: one position per workgroup when
+ *                       all fit on the device at once, else two; 2: two), or the
+ *                       ticketed chase (0).  Same results bitwise.  Built in: 1.
  * Results depend on band_width and dc_leaf only through rounding; every
  * parameter value gives a correct solve.  A batched instance and a single solve
  * of the same order use the same values.

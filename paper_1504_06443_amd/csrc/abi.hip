@@ -224,6 +224,9 @@ BulgeChase chase_of(const Plan& p) {
   c.n = p.M; c.b = p.b; c.band = p.band; c.ldband = p.ldband; c.d = p.d; c.e = p.e;
   c.V = p.V2; c.tau = p.tau2; c.kmax = p.kmax; c.sync = p.sync; c.err = p.err;
   c.info = p.info;
+  // the phase scratch is idle between S1 and S3
+  c.msg = (double*)p.scratch;
+  c.msg_bytes = p.scratch_bytes;
   return c;
 }
 
@@ -276,7 +279,11 @@ void solve_one(int64_t M, const double* A, int64_t lda, const double* B, int64_t
     sy2sb(r, sa, s);
   }
   if (pp) pp->mark(3);
-  sb2st(chase_of(p), s);
+  {
+    BulgeChase c = chase_of(p);
+    c.coop = coop;
+    sb2st(c, s);
+  }
   if (pp) pp->mark(4);
   if (!vectors) {
     stebz_ws(M, p.d, p.e, lambda, p.bounds, s);
@@ -330,7 +337,11 @@ void sep_vectors(const Plan& p, double* lam, double* Z, int64_t ldz, int32_t* in
     r.coop = true;
     sy2sb(r, sa, s);
   }
-  sb2st(chase_of(p), s);
+  {
+    BulgeChase c = chase_of(p);
+    c.coop = true;
+    sb2st(c, s);
+  }
   {
     Arena sa = scratch_arena(p);
     stedc(M, p.d, p.e, lam, Z, ldz, info, sa, s);
@@ -1189,6 +1200,9 @@ int gep_tridiagonalize(int64_t M, const double* C, int64_t ldc, int band_width, 
     c.e = e_or_dummy;
     c.V = nullptr; c.tau = nullptr; c.kmax = M > 1 ? cdiv(M - 1, b) : 1;
     c.sync = sync; c.err = err;
+    c.coop = true;
+    c.msg = (double*)sa.base;  // the band reduction's workspace, idle now
+    c.msg_bytes = sa.cap;
     sb2st(c, s);
     return GEP_OK;
   });

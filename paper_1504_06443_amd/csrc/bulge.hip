@@ -420,6 +420,328 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
   }
 }
 
+// ------------------------------------------------------------ data-stationary chase
+// Each workgroup owns P consecutive positions of every sweep: their diagonal blocks
+// D and the blocks E to their left stay in LDS from one sweep to the next.  From
+// sweep s to s + 1 a window moves down one row: D loses its first row and column, E
+// loses its first row and column and takes D's first column (below the diagonal)
+// as its last column.  The one new row at the bottom is row r + b of the matrix,
+// which position k + 1 finished at sweep s: D gets that position's E(0, 1..b-1) and
+// D(0, 0), E gets zeros and, last, E(0, 0) (the band element at distance b; every
+// entry further out in that row was annihilated by earlier sweeps).  Position k - 1
+// passes the reflector that E(s, k) needs.  A step therefore receives b + 1 numbers
+// from each neighbour instead of loading both blocks from the band and storing them
+// back, which was most of the latency on the chain of dependent steps ((s, k) after
+// (s - 1, k + 1) and (s, k - 1)).  Between positions of one workgroup the numbers
+// stay in LDS; between workgroups they go through memory with a flag, and the
+// reflector is sent as soon as it is formed.  Every step does the ticket kernel's
+// arithmetic on the same values (D mirrored from its lower triangle, as the band
+// load does), so the two kernels give the same bits.  Position 0 writes the
+// tridiagonal entries to the band as they become final.  All workgroups run at
+// once, so the launch is cooperative.
+struct StatArgs {
+  ChaseArgs c;
+  int64_t npos0;    // positions of the first sweep
+  double* msg;      // per position: forward (v, tau) and backward (E row 0, D(0,0)),
+                    // each double buffered by sweep parity, MSG doubles apiece
+  int32_t* fwdf;    // per position: sweeps whose forward message is published
+  int32_t* backf;   // per position: sweeps whose backward message is published
+};
+
+constexpr int MSG = MAXB + 1;
+
+__device__ inline double* fwd_msg(const StatArgs& x, int64_t k, int par) {
+  return x.msg + (4 * k + par) * MSG;
+}
+__device__ inline double* back_msg(const StatArgs& x, int64_t k, int par) {
+  return x.msg + (4 * k + 2 + par) * MSG;
+}
+
+// Waits until *f1 >= n1 and *f2 >= n2 (a null flag is no condition); false on an
+// error or time-out, as wait_for.
+__device__ bool wait_two(const ChaseArgs& a, const int32_t* f1, int32_t n1, const int32_t* f2,
+                         int32_t n2) {
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    const bool ok1 =
+        !f1 || __hip_atomic_load(f1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n1;
+    const bool ok2 =
+        !f2 || __hip_atomic_load(f2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= n2;
+    if (ok1 && ok2) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      return true;
+    }
+    if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+    if (a.force_fail || wall_clock64() - t0 > a.timeout_ticks) {
+      __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return false;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+
+// last sweep with a position k (position k of sweep s starts at row s + 1 + k b)
+__device__ inline int64_t stat_last_sweep(const ChaseArgs& a, int64_t k) {
+  const int64_t s = a.n - 2 - k * a.b;
+  return s < a.nsweeps - 1 ? s : a.nsweeps - 1;
+}
+
+template <int P>
+__global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
+  __shared__ double Es[P][MAXB * LDS_LD];
+  __shared__ double Ds[P][MAXB * LDS_LD];
+  __shared__ double v[MAXB], vprev[MAXB], p[MAXB], xcol[MAXB], msgin[MSG];
+  __shared__ double locb[P][MSG];   // backward message of position q + 1, in LDS
+  __shared__ double sh[8];
+  __shared__ double tprev_sh;
+  __shared__ int ok_sh;
+  const ChaseArgs& a = x.c;
+  const int tid = threadIdx.x;
+  const int b = a.b;
+  const int64_t n = a.n;
+  const int64_t ld = a.ldband;
+  double* band = a.band;
+  const int64_t k0 = (int64_t)blockIdx.x * P;
+  int np = (int)((x.npos0 - k0) < P ? (x.npos0 - k0) : P);  // positions owned
+  if (np <= 0) return;
+  // sweep 0's blocks from the band: D (lower triangle, mirrored), and E (b columns)
+  // or, for position 0, column 0 below the diagonal
+  for (int q = 0; q < np; ++q) {
+    const int64_t k = k0 + q;
+    const int64_t r = 1 + k * b;
+    const int L = (int)((n - r) < b ? (n - r) : b);
+    const int64_t c = r - b;
+    const int i = tid & 63, j0 = tid >> 6;
+    double xd[PER], xe[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int j = j0 + CW * m;
+      const bool okd = i < L && j <= i;
+      xd[m] = cld(&band[okd ? (i - j) + (r + j) * ld : 0]);
+    }
+    if (k > 0) {
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = j0 + CW * m;
+        const bool oke = i < L && j < b;
+        xe[m] = cld(&band[oke ? (b + i - j) + (c + j) * ld : 0]);
+      }
+    }
+    double xv = 0.0;
+    if (k == 0 && tid < L) xv = cld(&band[1 + tid]);
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int j = j0 + CW * m;
+      if (i < L && j <= i) {
+        Ds[q][i + j * LDS_LD] = xd[m];
+        Ds[q][j + i * LDS_LD] = xd[m];
+      }
+    }
+    if (k > 0) {
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int j = j0 + CW * m;
+        if (i < L && j < b) Es[q][i + j * LDS_LD] = xe[m];
+      }
+    }
+    if (k == 0 && tid < L) xcol[tid] = xv;
+  }
+  __syncthreads();
+  double tau_loc = 0.0;  // tau of the previous position of this workgroup, this sweep
+  const int64_t s_end = stat_last_sweep(a, k0);
+  for (int64_t s = 0; s <= s_end; ++s) {
+    for (int q = 0; q < np; ++q) {
+      const int64_t k = k0 + q;
+      if (s > stat_last_sweep(a, k)) break;  // later positions end earlier
+      double* D = Ds[q];
+      double* E = Es[q];
+      const int64_t r = s + 1 + k * b;
+      const int L = (int)((n - r) < b ? (n - r) : b);
+      const int Lprev = b;                    // position k - 1 always has a full reflector
+      const bool has_new = s >= 1 && L == b;  // row r + b - 1 came from position k + 1
+      const bool send_fwd = r + b <= n - 1;   // position k + 1 exists at this sweep
+      const bool fwd_remote = q == 0 && k >= 1;        // reflector from another workgroup
+      const bool back_remote = q == np - 1 && has_new;  // new row from another workgroup
+      if (fwd_remote || back_remote) {
+        if (tid == 0) {
+          ok_sh = wait_two(a, fwd_remote ? &x.fwdf[k - 1] : nullptr, (int32_t)(s + 1),
+                           back_remote ? &x.backf[k + 1] : nullptr, (int32_t)s)
+                      ? 1
+                      : 0;
+        }
+        __syncthreads();
+        if (!ok_sh) return;
+      }
+      if (has_new && tid <= b)
+        msgin[tid] = back_remote ? cld(&back_msg(x, k + 1, (int)((s - 1) & 1))[tid]) : locb[q][tid];
+      if (k >= 1) {
+        if (fwd_remote) {
+          const double* fm = fwd_msg(x, k - 1, (int)(s & 1));
+          if (tid < b) vprev[tid] = cld(&fm[tid]);
+          if (tid == b) tprev_sh = cld(&fm[b]);
+        } else {
+          if (tid < b) vprev[tid] = v[tid];
+          if (tid == b) tprev_sh = tau_loc;
+        }
+      }
+      __syncthreads();
+      if (has_new && tid < b) {
+        const int qq = b - 1, j = tid;
+        const double dv = j < qq ? msgin[j + 1] : msgin[b];
+        D[qq + j * LDS_LD] = dv;
+        D[j + qq * LDS_LD] = dv;
+        if (k >= 1) E[qq + j * LDS_LD] = j == qq ? msgin[0] : 0.0;
+      }
+      // position 0: the column to annihilate, its last entry new from position 1
+      if (k == 0 && tid < L) v[tid] = (has_new && tid == b - 1) ? msgin[0] : xcol[tid];
+      const double tau_prev = k >= 1 ? tprev_sh : 0.0;
+      __syncthreads();
+      double beta, tau;
+      if (k == 0) {
+        house(L, v, sh, beta, tau);
+      } else {
+        // E <- E (I - tau_prev vprev vprev^T)
+        if (tau_prev != 0.0) {
+          matvec(L, Lprev, E, 1, LDS_LD, vprev, tau_prev, p);
+          __syncthreads();
+          {
+            const int i = tid & 63, j0 = tid >> 6;
+            if (i < L) {
+              const double pi = p[i];
+              double e[PER], vv[PER];
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + CW * m;
+                const int jc = j < Lprev ? j : 0;
+                e[m] = E[i + jc * LDS_LD];
+                vv[m] = vprev[jc];
+              }
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + CW * m;
+                if (j < Lprev) E[i + j * LDS_LD] = e[m] - pi * vv[m];
+              }
+            }
+          }
+          __syncthreads();
+        }
+        house_from(L, E, v, beta, tau);
+      }
+      // the reflector is complete: send it on at once if position k + 1 is in the
+      // next workgroup
+      const bool fwd_out = send_fwd && q == np - 1;
+      if (fwd_out) {
+        double* fm = fwd_msg(x, k, (int)(s & 1));
+        if (tid < L) cst(&fm[tid], v[tid]);
+        if (tid == 0) cst(&fm[b], tau);
+        __syncthreads();
+        if (tid == 0)
+          __hip_atomic_store(&x.fwdf[k], (int32_t)(s + 1), __ATOMIC_RELEASE,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      }
+      if (k >= 1) {
+        if (tau != 0.0) {
+          matvec(Lprev, L, E, LDS_LD, 1, v, tau, p);
+          __syncthreads();
+          {
+            const int i = tid & 63, j0 = tid >> 6;
+            if (i < L) {
+              const double vi = v[i];
+              double e[PER], pp[PER];
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + CW * m;
+                const int jc = j < Lprev ? j : 0;
+                e[m] = E[i + jc * LDS_LD];
+                pp[m] = p[jc];
+              }
+#pragma unroll
+              for (int m = 0; m < PER; ++m) {
+                const int j = j0 + CW * m;
+                if (j >= 1 && j < Lprev) E[i + j * LDS_LD] = e[m] - vi * pp[m];
+              }
+            }
+          }
+        }
+        if (tid == 0) E[0] = beta;
+        if (tid >= 1 && tid < L) E[tid] = 0.0;
+        __syncthreads();
+      }
+      if (tau != 0.0) two_sided(L, D, v, tau, p);
+      // the row that leaves the window: to the previous workgroup now, or kept in
+      // LDS for this workgroup's previous position
+      if (k >= 1) {
+        if (q == 0) {
+          double* bm = back_msg(x, k, (int)(s & 1));
+          if (tid < b) cst(&bm[tid], E[tid * LDS_LD]);
+          if (tid == b) cst(&bm[b], D[0]);
+          __syncthreads();
+          if (tid == 0)
+            __hip_atomic_store(&x.backf[k], (int32_t)(s + 1), __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          if (tid < b) locb[q - 1][tid] = E[tid * LDS_LD];
+          if (tid == b) locb[q - 1][b] = D[0];
+        }
+      }
+      tau_loc = tau;
+      // the tridiagonal entries (position 0) and the reflector for the back
+      // transformation
+      if (k == 0) {
+        if (tid == 0) cst(&band[1 + s * ld], beta);
+        if (tid >= 1 && tid < L) cst(&band[(1 + tid) + s * ld], 0.0);
+        // row r leaves the window: its diagonal entry is final
+        if (tid == 0) cst(&band[r * ld], D[0]);
+        if (s == s_end) {
+          // the last window: its lower triangle is final
+          const int i = tid & 63, j0 = tid >> 6;
+          if (i < L)
+#pragma unroll
+            for (int m = 0; m < PER; ++m) {
+              const int j = j0 + CW * m;
+              if (j <= i) cst(&band[(i - j) + (r + j) * ld], D[i + j * LDS_LD]);
+            }
+        }
+      }
+      if (a.V) {
+        const int64_t j = s / NBW;
+        const int cc = (int)(s % NBW);
+        double* blk = a.V + (j * a.kmax + k) * (int64_t)(HP * NBW);
+        if (tid < L) cst(&blk[(cc + tid) * NBW + cc], v[tid]);
+        if (tid == 0) cst(&a.tau[s * a.kmax + k], tau);
+      }
+      if (s < stat_last_sweep(a, k)) {
+        // move the window down one row (D read from its lower triangle)
+        const int i = tid & 63, j0 = tid >> 6;
+        double dn[PER], en[PER];
+        double xn = 0.0;
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+          const int j = j0 + CW * m;
+          const int hi = i > j ? i : j, lo = i > j ? j : i;
+          const bool okd = i < L - 1 && j < L - 1;
+          dn[m] = D[okd ? (hi + 1) + (lo + 1) * LDS_LD : 0];
+          if (k >= 1) {
+            const bool oke = i < L - 1 && j < b;
+            const int src = !oke ? 0 : (j < b - 1 ? (i + 1) + (j + 1) * LDS_LD : (i + 1));
+            en[m] = j < b - 1 ? E[src] : D[src];
+          }
+        }
+        if (k == 0 && tid < L - 1) xn = D[tid + 1];
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+          const int j = j0 + CW * m;
+          if (i < L - 1 && j < L - 1) D[i + j * LDS_LD] = dn[m];
+          if (k >= 1 && i < L - 1 && j < b) E[i + j * LDS_LD] = en[m];
+        }
+        if (k == 0 && tid < L - 1) xcol[tid] = xn;
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void extract_tridiag(int64_t n, const double* __restrict__ band, int64_t ld,
                                 double* __restrict__ d, double* __restrict__ e) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1586,6 +1908,28 @@ size_t sb2st_block_storage(int64_t n, int b) {
   return (size_t)ngroups * kmax * HP * NBW;
 }
 
+size_t sb2st_message_bytes(int64_t n, int b) {
+  const int64_t npos0 = n > 2 && b > 0 ? (n - 2) / b + 1 : 0;
+  return (size_t)(4 * npos0 * MSG) * sizeof(double);
+}
+
+namespace {
+// Workgroups of the data-stationary chase (P positions each) that can be resident
+// at once.
+template <int P>
+int64_t stationary_capacity() {
+  static const int64_t cached = [] {
+    int dev = 0, cus = 0, per = 0;
+    GEP_HIP(hipGetDevice(&dev));
+    GEP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    GEP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)chase_stationary<P>,
+                                                         CNT, 0));
+    return (int64_t)cus * per;
+  }();
+  return cached;
+}
+}  // namespace
+
 void sb2st(const BulgeChase& c, hipStream_t s) {
   const int64_t n = c.n;
   if (c.b > MAXB || c.b < 1) throw HipError{hipErrorInvalidValue, "band width"};
@@ -1607,12 +1951,37 @@ void sb2st(const BulgeChase& c, hipStream_t s) {
     // a sweep's positions are ever worked on at once: more workgroups would only
     // spin (and, in batched solves, keep other instances' chases off the CUs).
     const int64_t npos0 = (n - 2) / c.b + 1;
-    int64_t groups = npos0 / 2 + tune("chase_extra_groups", n);
-    if (groups > nsweeps) groups = nsweeps;
-    if (groups > 512) groups = 512;
+    // Data-stationary chase: one position per workgroup if all fit at once, else two
+    // (tuning value 2: two in any case)
+    int per_group = 0;
+    const int64_t mode = tune("chase_stationary", n);
+    if (c.coop && c.b >= 8 && c.msg && c.msg_bytes >= sb2st_message_bytes(n, c.b) &&
+        2 * npos0 <= n + 8 && mode >= 1) {
+      if (mode == 1 && npos0 <= stationary_capacity<1>())
+        per_group = 1;
+      else if (cdiv(npos0, 2) <= stationary_capacity<2>())
+        per_group = 2;
+    }
     ProbeScope probe(PROBE_CHASE, s, 6.0 * c.b * (double)n * (double)n);
-    hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(CNT), 0, s, a);
-    GEP_LAUNCH_CHECK();
+    if (per_group > 0) {
+      StatArgs x;
+      x.c = a;
+      x.npos0 = npos0;
+      x.msg = c.msg;
+      x.fwdf = c.sync;
+      x.backf = c.sync + npos0;
+      void* args[] = {&x};
+      const void* fn = per_group == 1 ? (const void*)chase_stationary<1>
+                                      : (const void*)chase_stationary<2>;
+      GEP_HIP(hipLaunchCooperativeKernel(fn, dim3((unsigned)cdiv(npos0, per_group)), dim3(CNT),
+                                         args, 0, s));
+    } else {
+      int64_t groups = npos0 / 2 + tune("chase_extra_groups", n);
+      if (groups > nsweeps) groups = nsweeps;
+      if (groups > 512) groups = 512;
+      hipLaunchKernelGGL(chase_kernel, dim3((unsigned)groups), dim3(CNT), 0, s, a);
+      GEP_LAUNCH_CHECK();
+    }
     raise_info_if(c.err, c.info, INFO_WAIT_TIMEOUT, s);
   }
   hipLaunchKernelGGL(extract_tridiag, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, s, n,

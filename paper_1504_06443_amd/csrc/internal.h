@@ -65,7 +65,14 @@ struct BulgeChase {
   int32_t* sync = nullptr; // device scratch: progress flags (n + 8 ints)
   int32_t* err = nullptr;  // device: set to nonzero if a wait timed out
   int32_t* info = nullptr; // device: INFO_WAIT_TIMEOUT if so (optional)
+  // Cooperative launches allowed (single solves): the data-stationary chase runs
+  // when msg holds at least sb2st_message_bytes(n, b) of device scratch, which it
+  // uses only while it runs.  Otherwise (batched solves) the ticketed chase.
+  bool coop = false;
+  double* msg = nullptr;
+  size_t msg_bytes = 0;
 };
+size_t sb2st_message_bytes(int64_t n, int b);
 size_t sb2st_reflector_count(int64_t n, int b);
 size_t sb2st_block_storage(int64_t n, int b);
 void sb2st(const BulgeChase& c, hipStream_t s);

@@ -44,6 +44,7 @@ const Param kParams[] = {
     {"chase_extra_groups", 0, 512},   // bulge chase workgroups beyond half the positions
     {"q2_mixed_fp32", 0, 1},          // mixed precision: Q2 in FP32 arithmetic (1) or FP64
     {"q2_staged", 0, 1},              // FP64 Q2: the DMA-staged 16-byte window kernel (1) or not
+    {"chase_stationary", 0, 2},       // single solves: data-stationary chase (1; 2: two positions per workgroup) or ticketed
 };
 
 bool known(const std::string& k, const Param** out) {
@@ -266,6 +267,7 @@ int64_t default_value(const std::string& k, int64_t M) {
   // V / T staged by direct-to-LDS loads and Z moved in 16-byte accesses: S4 at
   // M = 32768 1983 against 2355 ms with the register-staged kernel
   if (k == "q2_staged") return 1;
+  if (k == "chase_stationary") return 1;
   return -1;
 }
 

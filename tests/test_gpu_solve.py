@@ -314,6 +314,38 @@ def _tune_reset():
     _binding.lib().gep_tune_reset_overrides()
 
 
+@pytest.mark.parametrize("M,bw,mode", [(3, 0, 1), (4, 0, 1), (17, 0, 1), (100, 0, 1), (600, 0, 1),
+                                       (600, 8, 1), (601, 16, 1), (2080, 0, 1), (2113, 0, 1),
+                                       (3000, 0, 1), (4, 0, 2), (100, 0, 2), (129, 0, 2),
+                                       (600, 8, 2), (601, 16, 2), (2113, 0, 2), (3000, 0, 2)])
+def test_chase_stationary_matches_ticketed(gpu, M, bw, mode):
+    """The data-stationary bulge chase (each workgroup keeps its positions' blocks
+    in LDS across sweeps and passes b + 1 numbers to each neighbour) does the
+    ticketed chase's arithmetic on the same values: eigenvalues and eigenvectors
+    of a full solve, and the eigenvalues of a values-only solve, are bitwise equal
+    with either kernel (chase_stationary 1 or 2 against 0), with one or two
+    positions per workgroup (an odd count leaves the last workgroup one), at band
+    widths 8 .. 64, orders with a short last position, and orders too small for a
+    second position."""
+    say(f"[solve] stationary ({mode}) vs ticketed chase, M={M} band_width={bw}")
+    A, B = synth.banded_pair(M, max(2.0, np.sqrt(M / 8)), 1300 + M)
+    out = {}
+    for stat in (mode, 0):
+        _tune("chase_stationary", M, M, stat)
+        if bw:
+            _tune("band_width", M, M, bw)
+        try:
+            lam, Y = _gep().solve(to_gpu(A), to_gpu(B))
+            lamv, _ = _gep().solve(to_gpu(A), to_gpu(B), job="values")
+        finally:
+            _tune_reset()
+        out[stat] = (to_np(lam), to_np(Y), to_np(lamv))
+    for x1, x0 in zip(out[mode], out[0]):
+        assert np.array_equal(x1, x0)
+    if M <= 600:
+        check_against_oracle(A, B, out[mode][0], out[mode][1])
+
+
 @pytest.mark.parametrize("M", [2080, 2113, 3001])
 def test_solve_band64_wide_q2(gpu, M):
     """The Q2 back transformation with two 16-column groups per wave (one wave per
