@@ -425,7 +425,7 @@ def main() -> int:
     n_launch, dom_ms, dom_flops = probes[dom]
     avg_ms = dom_ms / max(n_launch, 1)
     achieved = (dom_flops / max(n_launch, 1)) / (avg_ms / 1e3) / 1e12 if n_launch else 0.0
-    bound = "alu" if dom in ("chase_kernel", "panel_qr_coop") else "mfma"
+    bound = "alu" if dom in ("chase", "panel_qr_coop") else "mfma"
     roofline = {"bound": bound, "achieved": achieved, "peak": PEAK_FP64, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64, "traffic": kernel_traffic(dom, workload),
                 "kernel": dom, "launches_per_step": n_launch / args.steps,

@@ -335,7 +335,7 @@ double gep_profile_dc_flops(void);
  * event pair on the stream it is launched on, with the launch's algorithmic
  * flops.  Kernels: 0 = the 128 x 128 interior GEMM tile kernel (flops 2 m n k,
  * or k n (n + 1) for a lower-triangle product), 1 = the Q2 application (2 n^2
- * ncols), 2 = the bulge chase (6 b n^2), 3 = the band-reduction panel QR
+ * ncols), 2 = the bulge chase, either kernel (6 b n^2), 3 = the band-reduction panel QR
  * (2 n w^2 - 2 w^3 / 3 for an n x w panel).
  * gep_probe_read synchronises on the recorded events, returns the number of
  * launches, their summed duration in milliseconds and their summed flops since

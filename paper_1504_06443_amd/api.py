@@ -259,7 +259,7 @@ def profile_read() -> dict:
     return {PHASES[i]: buf[i] for i in range(n)}
 
 
-PROBE_KERNELS = ("dgemm_fast_kernel", "q2_apply", "chase_kernel", "panel_qr_coop")
+PROBE_KERNELS = ("dgemm_fast_kernel", "q2_apply", "chase", "panel_qr_coop")
 
 
 def probe_enable(on: bool = True) -> None:

@@ -1350,7 +1350,7 @@ const char* gep_probe_name(int kernel) {
   switch (kernel) {
     case PROBE_GEMM: return "dgemm_fast_kernel";
     case PROBE_Q2_APPLY: return "q2_apply";
-    case PROBE_CHASE: return "chase_kernel";
+    case PROBE_CHASE: return "chase";
     case PROBE_PANEL_QR: return "panel_qr_coop";
     default: return nullptr;
   }
