@@ -146,11 +146,10 @@ __device__ void house_from(int L, const double* x, double* vout, double& beta_ou
 
 // D (L x L symmetric, full in LDS, ld LDS_LD) <- H D H, H = I - tau v v^T.
 // 4 threads per row for the matrix-vector product.
-__device__ void two_sided(int L, double* D, const double* v, double tau, double* p) {
+// Second half of two_sided, after p = tau D v: D <- D - v w^T - w v^T with
+// w = p - a v.  No barrier at the end.
+__device__ void two_sided_update(int L, double* D, const double* v, double tau, const double* p) {
   const int tid = threadIdx.x;
-  if (tau == 0.0) return;
-  matvec(L, L, D, 1, LDS_LD, v, tau, p);
-  __syncthreads();
   // a = tau p^T v / 2, formed by every wave (identical bits on every lane)
   const int lane = tid & 63;
   const double a = 0.5 * tau * wave_sum(lane < L ? p[lane] * v[lane] : 0.0);
@@ -175,7 +174,37 @@ __device__ void two_sided(int L, double* D, const double* v, double tau, double*
       }
     }
   }
+}
+
+__device__ void two_sided(int L, double* D, const double* v, double tau, double* p) {
+  if (tau == 0.0) return;
+  matvec(L, L, D, 1, LDS_LD, v, tau, p);
   __syncthreads();
+  two_sided_update(L, D, v, tau, p);
+  __syncthreads();
+}
+
+// E (L x Lprev) <- H E on columns 1.., H = I - tau v v^T, after p = tau E^T v
+// (column 0 is set to beta e_1 by the caller).  No barrier.
+__device__ void left_update(int L, int Lprev, double* E, const double* v, const double* p) {
+  const int tid = threadIdx.x;
+  const int i = tid & 63, j0 = tid >> 6;
+  if (i < L) {
+    const double vi = v[i];
+    double e[PER], pp[PER];
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int j = j0 + CW * m;
+      const int jc = j < Lprev ? j : 0;
+      e[m] = E[i + jc * LDS_LD];
+      pp[m] = p[jc];
+    }
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int j = j0 + CW * m;
+      if (j >= 1 && j < Lprev) E[i + j * LDS_LD] = e[m] - vi * pp[m];
+    }
+  }
 }
 
 struct ChaseArgs {
@@ -335,25 +364,7 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
           // p[col] = tau v^T E(:, col); column 0 is replaced by beta e_1 below
           matvec(Lprev, L, Es, LDS_LD, 1, v, tau, p);
           __syncthreads();
-          {
-            const int i = tid & 63, j0 = tid >> 6;
-            if (i < L) {
-              const double vi = v[i];
-              double e[PER], pp[PER];
-#pragma unroll
-              for (int m = 0; m < PER; ++m) {
-                const int j = j0 + CW * m;
-                const int jc = j < Lprev ? j : 0;
-                e[m] = Es[i + jc * LDS_LD];
-                pp[m] = p[jc];
-              }
-#pragma unroll
-              for (int m = 0; m < PER; ++m) {
-                const int j = j0 + CW * m;
-                if (j >= 1 && j < Lprev) Es[i + j * LDS_LD] = e[m] - vi * pp[m];
-              }
-            }
-          }
+          left_update(L, Lprev, Es, v, p);
         }
         if (tid == 0) Es[0] = beta;
         if (tid >= 1 && tid < L) Es[tid] = 0.0;
@@ -490,7 +501,7 @@ template <int P>
 __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
   __shared__ double Es[P][MAXB * LDS_LD];
   __shared__ double Ds[P][MAXB * LDS_LD];
-  __shared__ double v[MAXB], vprev[MAXB], p[MAXB], xcol[MAXB], msgin[MSG];
+  __shared__ double v[MAXB], vprev[MAXB], p[MAXB], p2[MAXB], xcol[MAXB];
   __shared__ double locb[P][MSG];   // backward message of position q + 1, in LDS
   __shared__ double sh[8];
   __shared__ double tprev_sh;
@@ -572,8 +583,26 @@ __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
         __syncthreads();
         if (!ok_sh) return;
       }
-      if (has_new && tid <= b)
-        msgin[tid] = back_remote ? cld(&back_msg(x, k + 1, (int)((s - 1) & 1))[tid]) : locb[q][tid];
+      // the new bottom row: its D entries, E's zeros and band element, and for
+      // position 0 the last entry of the column to annihilate
+      if (has_new && tid < b) {
+        const double* bm = back_remote ? back_msg(x, k + 1, (int)((s - 1) & 1)) : locb[q];
+        const int qq = b - 1, j = tid;
+        const int src = j < qq ? j + 1 : b;
+        const double dv = back_remote ? cld(&bm[src]) : bm[src];
+        D[qq + j * LDS_LD] = dv;
+        D[j + qq * LDS_LD] = dv;
+        if (j == qq) {
+          const double e0 = back_remote ? cld(&bm[0]) : bm[0];
+          if (k >= 1)
+            E[qq + j * LDS_LD] = e0;
+          else
+            v[qq] = e0;
+        } else if (k >= 1) {
+          E[qq + j * LDS_LD] = 0.0;
+        }
+      }
+      if (k == 0 && tid < L && !(has_new && tid == b - 1)) v[tid] = xcol[tid];
       if (k >= 1) {
         if (fwd_remote) {
           const double* fm = fwd_msg(x, k - 1, (int)(s & 1));
@@ -585,17 +614,7 @@ __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
         }
       }
       __syncthreads();
-      if (has_new && tid < b) {
-        const int qq = b - 1, j = tid;
-        const double dv = j < qq ? msgin[j + 1] : msgin[b];
-        D[qq + j * LDS_LD] = dv;
-        D[j + qq * LDS_LD] = dv;
-        if (k >= 1) E[qq + j * LDS_LD] = j == qq ? msgin[0] : 0.0;
-      }
-      // position 0: the column to annihilate, its last entry new from position 1
-      if (k == 0 && tid < L) v[tid] = (has_new && tid == b - 1) ? msgin[0] : xcol[tid];
       const double tau_prev = k >= 1 ? tprev_sh : 0.0;
-      __syncthreads();
       double beta, tau;
       if (k == 0) {
         house(L, v, sh, beta, tau);
@@ -639,35 +658,22 @@ __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
           __hip_atomic_store(&x.fwdf[k], (int32_t)(s + 1), __ATOMIC_RELEASE,
                              __HIP_MEMORY_SCOPE_AGENT);
       }
+      // H applied to E from the left and to D from both sides: the two products
+      // with v in one phase, the two updates in the next
       if (k >= 1) {
         if (tau != 0.0) {
           matvec(Lprev, L, E, LDS_LD, 1, v, tau, p);
+          matvec(L, L, D, 1, LDS_LD, v, tau, p2);
           __syncthreads();
-          {
-            const int i = tid & 63, j0 = tid >> 6;
-            if (i < L) {
-              const double vi = v[i];
-              double e[PER], pp[PER];
-#pragma unroll
-              for (int m = 0; m < PER; ++m) {
-                const int j = j0 + CW * m;
-                const int jc = j < Lprev ? j : 0;
-                e[m] = E[i + jc * LDS_LD];
-                pp[m] = p[jc];
-              }
-#pragma unroll
-              for (int m = 0; m < PER; ++m) {
-                const int j = j0 + CW * m;
-                if (j >= 1 && j < Lprev) E[i + j * LDS_LD] = e[m] - vi * pp[m];
-              }
-            }
-          }
+          left_update(L, Lprev, E, v, p);
+          two_sided_update(L, D, v, tau, p2);
         }
         if (tid == 0) E[0] = beta;
         if (tid >= 1 && tid < L) E[tid] = 0.0;
         __syncthreads();
+      } else if (tau != 0.0) {
+        two_sided(L, D, v, tau, p);
       }
-      if (tau != 0.0) two_sided(L, D, v, tau, p);
       // the row that leaves the window: to the previous workgroup now, or kept in
       // LDS for this workgroup's previous position
       if (k >= 1) {
