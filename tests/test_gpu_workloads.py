@@ -3,9 +3,10 @@
 configuration the benchmark times (one gep_solve on the current stream).
 
 Eigenvalues are compared with the CPU oracle's, stored by
-tests/golden/make_golden.py (which calls only oracle/): all eigenvalues where
-the oracle's full solve is affordable (8192), and the exact number of
-eigenvalues below fixed shifts (Sylvester inertia of A - sigma B) at 32768.
+tests/golden/make_golden.py (which calls only oracle/): all eigenvalues at both
+sizes (the oracle's values-only solve at 32768 took six hours on 8 threads),
+and the exact number of eigenvalues below fixed shifts (Sylvester inertia of
+A - sigma B, an independent oracle route) where those counts are stored.
 Eigenvectors are checked through the invariants A Y = B Y Lambda and
 Y^T B Y = I, evaluated at full size with torch FP64 matmuls on the GPU
 (independent of libgep)."""
