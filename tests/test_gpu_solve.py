@@ -409,7 +409,8 @@ def test_solve_band64_staged_vs_register_q2(gpu, M):
 
 @pytest.mark.parametrize("key,value", [("band_width", 8), ("band_width", 24), ("band_width", 48),
                                        ("band_width", 64), ("dc_leaf", 16), ("dc_leaf", 40),
-                                       ("chase_extra_groups", 0), ("symm_split_rows", 64)])
+                                       ("chase_extra_groups", 0), ("symm_split_rows", 64),
+                                       ("chase_stationary", 0), ("chase_stationary", 2)])
 def test_solve_tuned_parameters(gpu, key, value):
     """Every admissible value of a tuning-table parameter gives a correct solve:
     M = 600 against the oracle with one parameter overridden."""
