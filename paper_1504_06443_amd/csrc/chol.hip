@@ -12,7 +12,6 @@
 namespace gep {
 namespace {
 
-constexpr int NT = 256;
 constexpr int LDS_LD = NB + 1;
 
 // Factor the n x n (n <= NB) diagonal block in place (lower triangle; the upper
@@ -27,13 +26,18 @@ constexpr int LDS_LD = NB + 1;
 // X(i, 0:j) -= L(i,j) X(j, 0:j) for i > j), which is as parallel as the trailing
 // update; the strictly lower part of X is kept transposed in the unused upper
 // triangle of the LDS block (X(i,c) at row c, column i) and its diagonal in xd.
-__global__ void __launch_bounds__(NT)
+// LEAF_NT threads, TPC of them per column (trailing update) or row (inverse
+// update), so a column step is at most two rounds of eight elements per thread.
+constexpr int LEAF_NT = 1024;
+constexpr int TPC = LEAF_NT / NB;
+
+__global__ void __launch_bounds__(LEAF_NT)
 potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict__ linv,
                  int32_t* __restrict__ info, int64_t row0, int64_t info_add) {
   extern __shared__ double S[];  // column-major, ld LDS_LD
   double* xd = S + (size_t)NB * LDS_LD;
   const int tid = threadIdx.x;
-  for (int j = tid >> 7; j < n; j += NT / 128)
+  for (int j = tid >> 7; j < n; j += LEAF_NT / 128)
     for (int i = tid & 127; i < n; i += 128) S[i + j * LDS_LD] = (i >= j) ? a[i + j * lda] : 0.0;
   __syncthreads();
   for (int j = 0; j < n; ++j) {
@@ -47,52 +51,52 @@ potrf_trtri_leaf(int n, double* __restrict__ a, int64_t lda, double* __restrict_
       S[j + j * LDS_LD] = ljj;
       xd[j] = rl;
     }
-    for (int i = j + 1 + tid; i < n; i += NT) S[i + j * LDS_LD] *= rl;  // L(j+1:, j)
-    for (int c = tid; c < j; c += NT) S[c + j * LDS_LD] *= rl;          // X(j, 0:j)
+    for (int i = j + 1 + tid; i < n; i += LEAF_NT) S[i + j * LDS_LD] *= rl;  // L(j+1:, j)
+    for (int c = tid; c < j; c += LEAF_NT) S[c + j * LDS_LD] *= rl;          // X(j, 0:j)
     __syncthreads();
-    // trailing update of L's lower triangle: 2 threads per column, eight rows'
+    // trailing update of L's lower triangle: TPC threads per column, eight rows'
     // operands read before any of their updates is written (one LDS round trip
     // per eight elements instead of one per element)
-    for (int k = j + 1 + (tid >> 1); k < n; k += NT / 2) {
+    for (int k = j + 1 + tid / TPC; k < n; k += LEAF_NT / TPC) {
       const double lkj = S[k + j * LDS_LD];
-      int i = k + (tid & 1);
-      for (; i + 14 < n; i += 16) {
+      int i = k + tid % TPC;
+      for (; i + 7 * TPC < n; i += 8 * TPC) {
         double lj[8], sk[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          lj[u] = S[i + 2 * u + j * LDS_LD];
-          sk[u] = S[i + 2 * u + k * LDS_LD];
+          lj[u] = S[i + TPC * u + j * LDS_LD];
+          sk[u] = S[i + TPC * u + k * LDS_LD];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) S[i + 2 * u + k * LDS_LD] = sk[u] - lj[u] * lkj;
+        for (int u = 0; u < 8; ++u) S[i + TPC * u + k * LDS_LD] = sk[u] - lj[u] * lkj;
       }
-      for (; i < n; i += 2) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * lkj;
+      for (; i < n; i += TPC) S[i + k * LDS_LD] -= S[i + j * LDS_LD] * lkj;
     }
-    // X(i, 0:j+1) -= L(i,j) X(j, 0:j+1) for i > j: 2 threads per row, batched the
-    // same way
-    for (int i = j + 1 + (tid >> 1); i < n; i += NT / 2) {
+    // X(i, 0:j+1) -= L(i,j) X(j, 0:j+1) for i > j: TPC threads per row, batched
+    // the same way
+    for (int i = j + 1 + tid / TPC; i < n; i += LEAF_NT / TPC) {
       const double lij = S[i + j * LDS_LD];
-      int c = tid & 1;
-      for (; c + 14 < j; c += 16) {
+      int c = tid % TPC;
+      for (; c + 7 * TPC < j; c += 8 * TPC) {
         double xj[8], xi[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-          xj[u] = S[c + 2 * u + j * LDS_LD];
-          xi[u] = S[c + 2 * u + i * LDS_LD];
+          xj[u] = S[c + TPC * u + j * LDS_LD];
+          xi[u] = S[c + TPC * u + i * LDS_LD];
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) S[c + 2 * u + i * LDS_LD] = xi[u] - lij * xj[u];
+        for (int u = 0; u < 8; ++u) S[c + TPC * u + i * LDS_LD] = xi[u] - lij * xj[u];
       }
-      for (; c <= j; c += 2) {
+      for (; c <= j; c += TPC) {
         const double xjc = (c == j) ? rl : S[c + j * LDS_LD];
         S[c + i * LDS_LD] -= lij * xjc;
       }
     }
     __syncthreads();
   }
-  for (int j = tid >> 7; j < n; j += NT / 128)
+  for (int j = tid >> 7; j < n; j += LEAF_NT / 128)
     for (int i = tid & 127; i < n; i += 128) a[i + j * lda] = (i >= j) ? S[i + j * LDS_LD] : 0.0;
-  for (int j = tid >> 7; j < NB; j += NT / 128)
+  for (int j = tid >> 7; j < NB; j += LEAF_NT / 128)
     for (int i = tid & 127; i < NB; i += 128) {
       double x = 0.0;
       if (i < n && j < n && i >= j) x = (i == j) ? xd[j] : S[j + i * LDS_LD];
@@ -127,7 +131,7 @@ void potrf_leaf(int64_t n, double* a, int64_t lda, double* linv_blk, int32_t* in
     return true;
   }();
   (void)attr_set;
-  hipLaunchKernelGGL(potrf_trtri_leaf, dim3(1), dim3(NT), potrf_leaf_lds(), s, (int)n, a, lda,
+  hipLaunchKernelGGL(potrf_trtri_leaf, dim3(1), dim3(LEAF_NT), potrf_leaf_lds(), s, (int)n, a, lda,
                      linv_blk, info, row0, info_add);
   GEP_LAUNCH_CHECK();
 }
