@@ -23,8 +23,6 @@
 // last to first and, inside a group, positions in increasing k respects that.
 // Each workgroup owns a strip of columns of Z and applies every block to it in
 // that order (columns are independent), with the MFMA.
-#include <type_traits>
-
 #include "common.h"
 #include "internal.h"
 
@@ -108,9 +106,7 @@ __device__ inline void matvec(int nx, int ny, const double* M, int sx, int sy, c
   for (int m = 0; m < PER; ++m) {
     const int y = q + CW * m;
     const int yc = y < ny ? y : 0;
-    // rounded on its own (no fused multiply-add with the sum below), whether or
-    // not the bound is known at compile time
-    const double prod = __dmul_rn(M[xc * sx + yc * sy], w[yc]);
+    const double prod = M[xc * sx + yc * sy] * w[yc];
     t[m] = y < ny ? prod : 0.0;
   }
 #pragma unroll
@@ -288,16 +284,7 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
       __syncthreads();
       if (!ok_sh) return;
       const int64_t r = s + 1 + k * b;           // first row of this position
-      const int Lrt = (int)((n - r) < b ? (n - r) : b);  // reflector length
-      const int Lprev_rt = Lprev;
-      // The position in two copies, as in the data-stationary kernel, which gives
-      // the same bits only where both take the same copy: a full window at band
-      // width 64 with constant bounds, and the general one.
-      auto step = [&](auto full) {
-      constexpr bool FULL = decltype(full)::value;
-      const int b = FULL ? MAXB : a.b;
-      const int L = FULL ? MAXB : Lrt;
-      const int Lprev = FULL ? MAXB : Lprev_rt;
+      const int L = (int)((n - r) < b ? (n - r) : b);  // reflector length
       const int64_t c = r - b;                   // first column of the block left of D
       // load D (rows/cols r.., symmetric from the lower band) and the column
       // block to its left (column s for k = 0, the bulge block E otherwise).
@@ -435,14 +422,7 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
       }
       if (tid < L) vprev[tid] = v[tid];
       tau_prev = tau;
-      };
-      // (position k >= 1 follows a full reflector unless the sweep is shorter
-      // than that; the data-stationary kernel's condition agrees)
-      if (Lrt == MAXB && a.b == MAXB && (k == 0 || Lprev == MAXB))
-        step(std::true_type{});
-      else
-        step(std::false_type{});
-      Lprev = Lrt;
+      Lprev = L;
       __syncthreads();
       if (tid == 0)
         __hip_atomic_store(&a.progress[s], (int32_t)(k + 1), __ATOMIC_RELEASE,
@@ -587,15 +567,7 @@ __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
       double* D = Ds[q];
       double* E = Es[q];
       const int64_t r = s + 1 + k * b;
-      const int Lrt = (int)((n - r) < b ? (n - r) : b);
-      // The step, in two copies: one for a full window at band width 64 (nearly
-      // every step at b = 64), where every bound below is a constant and the
-      // clamps fold away, and the general one.  Same arithmetic in both (the
-      // products of matvec are rounded on their own in either copy).
-      auto step = [&](auto full) -> bool {
-      constexpr bool FULL = decltype(full)::value;
-      const int b = FULL ? MAXB : a.b;
-      const int L = FULL ? MAXB : Lrt;
+      const int L = (int)((n - r) < b ? (n - r) : b);
       const int Lprev = b;                    // position k - 1 always has a full reflector
       const bool has_new = s >= 1 && L == b;  // row r + b - 1 came from position k + 1
       const bool send_fwd = r + b <= n - 1;   // position k + 1 exists at this sweep
@@ -609,7 +581,7 @@ __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
                       : 0;
         }
         __syncthreads();
-        if (!ok_sh) return false;
+        if (!ok_sh) return;
       }
       // the new bottom row: its D entries, E's zeros and band element, and for
       // position 0 the last entry of the column to annihilate
@@ -772,10 +744,6 @@ __global__ void __launch_bounds__(CNT) chase_stationary(StatArgs x) {
         if (k == 0 && tid < L - 1) xcol[tid] = xn;
       }
       __syncthreads();
-      return true;
-      };
-      const bool ok = (Lrt == MAXB && b == MAXB) ? step(std::true_type{}) : step(std::false_type{});
-      if (!ok) return;
     }
   }
 }
