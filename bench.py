@@ -92,6 +92,13 @@ def cpu_baseline(M_target: int, sample: int) -> dict:
                                  "routine": "scipy.linalg.eigh(A, B, driver='gvd')"}
     except Exception as exc:  # context only; never fails the benchmark
         out["lapack_context"] = {"error": repr(exc)}
+    # context: the oracle's one measured run at the full order (values only, the
+    # run that wrote the stored eigenvalues; a vectors solve costs more)
+    meta = os.path.join(ROOT, "tests", "golden", f"m{M_target}.json")
+    if os.path.exists(meta):
+        m = json.load(open(meta))
+        out["full_size_values_only"] = {"seconds": m["oracle_seconds"], "threads": m["oracle_threads"],
+                                        "steps": m["steps"]}
     return out
 
 
