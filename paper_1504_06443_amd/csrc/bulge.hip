@@ -251,7 +251,7 @@ __device__ bool wait_for(const ChaseArgs& a, int64_t s, int32_t need) {
 __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
   __shared__ double Es[MAXB * LDS_LD];
   __shared__ double Ds[MAXB * LDS_LD];
-  __shared__ double v[MAXB], vprev[MAXB], p[MAXB];
+  __shared__ double v[MAXB], vprev[MAXB], p[MAXB], p2[MAXB];
   __shared__ double sh[8];
   __shared__ int64_t s_sh;
   __shared__ int ok_sh;
@@ -331,6 +331,8 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
       double beta, tau;
       if (k == 0) {
         house(L, v, sh, beta, tau);
+        // diagonal block rows/cols r .. r+L-1 <- H D H
+        if (tau != 0.0) two_sided(L, Ds, v, tau, p);
       } else {
         // E <- E (I - tau_prev vprev vprev^T)
         if (tau_prev != 0.0) {
@@ -360,21 +362,23 @@ __global__ void __launch_bounds__(CNT) chase_kernel(ChaseArgs a) {
         // reflector from column 0 of E (read in place), applied from the left to
         // columns 1..
         house_from(L, Es, v, beta, tau);
+        // H from the left on E (p[col] = tau v^T E(:, col); column 0 is replaced by
+        // beta e_1 below) and from both sides on the diagonal block D: the two
+        // products with v in one phase, the two updates in the next
         if (tau != 0.0) {
-          // p[col] = tau v^T E(:, col); column 0 is replaced by beta e_1 below
           matvec(Lprev, L, Es, LDS_LD, 1, v, tau, p);
+          matvec(L, L, Ds, 1, LDS_LD, v, tau, p2);
           __syncthreads();
           left_update(L, Lprev, Es, v, p);
+          two_sided_update(L, Ds, v, tau, p2);
         }
         if (tid == 0) Es[0] = beta;
         if (tid >= 1 && tid < L) Es[tid] = 0.0;
         __syncthreads();
       }
-      // diagonal block rows/cols r .. r+L-1 <- H D H.  The task's band stores are
-      // all issued after its arithmetic: the wait for a load's data also waits for
-      // every store issued before that load, and the release below has to wait
-      // for the stores anyway.
-      if (tau != 0.0) two_sided(L, Ds, v, tau, p);
+      // The task's band stores are all issued after its arithmetic: the wait for a
+      // load's data also waits for every store issued before that load, and the
+      // release below has to wait for the stores anyway.
       if (k == 0) {
         if (tid == 0) cst(&band[1 + s * ld], beta);
         if (tid >= 1 && tid < L) cst(&band[(1 + tid) + s * ld], 0.0);
