@@ -86,6 +86,9 @@ size_t gep_workspace_size(int64_t M, int job, int prec);
 /*
  * Solve A Y = B Y Lambda (all eigenpairs, or eigenvalues only for
  * job = GEP_JOB_VALUES, the paper's T_evo case of section 4).
+ * The call can be captured in a HIP graph and replayed (so can gep_solve_noalloc
+ * and gep_solve_lowest): on a capturing stream the workgroup-synchronised kernels
+ * are launched without the cooperative attribute, with identical results.
  *   A [lda x M], B [ldb x M]: lower triangles read.
  *   lambda [M]: eigenvalues, ascending.
  *   Y [ldy x M]: B-orthonormal eigenvectors (unused and may be NULL for VALUES).

@@ -242,6 +242,19 @@ int guarded(F&& f) {
   }
 }
 
+// True while s is being captured into a graph.  A single solve captured that way
+// launches the panel QR and the bulge chase as plain launches, the form batched
+// solves use: the same kernels with the same arithmetic, so the same results.  The
+// panel QR's grid is no larger than the device holds at once and its barrier wait
+// is bounded (a timeout reaches info); the ticketed chase hands out its work in
+// order, so no workgroup waits on one that has not started.  No phase events are
+// recorded.
+bool stream_capturing(hipStream_t s) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  GEP_HIP(hipStreamIsCapturing(s, &cs));
+  return cs != hipStreamCaptureStatusNone;
+}
+
 // One generalized eigenproblem, enqueued on s (arguments already validated).
 // coop: launch the panel QR cooperatively (co-residency guaranteed by the runtime);
 // prof: record the phase events.  mixed (vectors only): the interior GEMM tiles of
@@ -787,8 +800,9 @@ int gep_solve(int64_t M, const double* A, int64_t lda, const double* B, int64_t 
   if (ws_bytes < need) return GEP_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   return guarded([&]() -> int {
+    const bool eager = !stream_capturing(s);
     solve_one(M, A, lda, B, ldb, lambda, Y, ldy, job == GEP_JOB_VECTORS, workspace, ws_bytes, info,
-              s, true, true, prec == GEP_PREC_MIXED);
+              s, eager, eager, prec == GEP_PREC_MIXED);
     return GEP_OK;
   });
 }
@@ -818,7 +832,7 @@ int gep_solve_noalloc(int64_t M, const double* A, int64_t lda, const double* B, 
     void* ws = scratch_on_current_device();
     // no phase events: creating them is the one resource a profiled gep_solve adds
     solve_one(M, A, lda, B, ldb, lambda, Y, ldy, job == GEP_JOB_VECTORS, ws, NOALLOC_BYTES, info,
-              s, true, false, prec == GEP_PREC_MIXED);
+              s, !stream_capturing(s), false, prec == GEP_PREC_MIXED);
     return GEP_OK;
   });
 }
@@ -853,7 +867,8 @@ int gep_solve_lowest(int64_t M, const double* A, int64_t lda, const double* B, i
   if (ws_bytes < gep_workspace_size_lowest(M, k)) return GEP_ERR_WORKSPACE;
   hipStream_t s = (hipStream_t)stream;
   return guarded([&]() -> int {
-    solve_one(M, A, lda, B, ldb, lambda, Y, ldy, true, workspace, ws_bytes, info, s, true, true,
+    const bool eager = !stream_capturing(s);
+    solve_one(M, A, lda, B, ldb, lambda, Y, ldy, true, workspace, ws_bytes, info, s, eager, eager,
               false, k);
     return GEP_OK;
   });
