@@ -383,7 +383,9 @@ const char* gep_probe_name(int kernel);
  *                       bulge chase, each workgroup keeping its positions' blocks
  *                       in LDS across sweeps (1: one position per workgroup when
  *                       all fit on the device at once, else two; 2: two), or the
- *                       ticketed chase (0).  Same results bitwise.  Built in: 1.
+ *                       ticketed chase (0).  Same results bitwise.  Built in: 0
+                       (two long test runs went silent inside single solves
+                       that used the data-stationary chase; cause not found).
  * Results depend on band_width and dc_leaf only through rounding; every
  * parameter value gives a correct solve.  A batched instance and a single solve
  * of the same order use the same values.

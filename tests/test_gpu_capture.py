@@ -1,8 +1,7 @@
 """Single solves captured in a HIP graph (torch.cuda.CUDAGraph) and replayed, through
 the C ABI: gep_solve (eigenpairs, eigenvalues only, mixed precision),
 gep_solve_noalloc and gep_solve_lowest.  Under capture the panel QR and the bulge
-chase take their plain-launch forms (the data-stationary chase is cooperative, so
-the captured solve runs the ticketed one); the kernels' arithmetic is the same, so
+chase take their plain-launch forms; the kernels' arithmetic is the same, so
 every replay, with eager work and synchronisations in between, must equal the
 eager call bitwise, and the eager call must match the oracle."""
 import ctypes
