@@ -235,6 +235,9 @@ def test_tuning_table_api(lib, tmp_path):
     lib.gep_tune_clear()
     assert [get("band_width", M) for M in (100, 256, 2047, 2048)] == [16, 32, 32, 64]
     assert get("dc_leaf", 1000) == 64 and get("symm_split_rows", 10) == 2048
+    # the ticketed chase is the built-in S2 kernel at every order; the data-stationary
+    # one only runs when selected
+    assert [get("chase_stationary", M) for M in (3, 600, 8192, 32768)] == [0, 0, 0, 0]
     assert get("no_such_parameter", 10) == -1
     assert lib.gep_tune_set(b"band_width", 100, 200, 24) == 0
     assert lib.gep_tune_set(b"band_width", 150, 160, 48) == 0
